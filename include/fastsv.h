@@ -1,0 +1,140 @@
+/*
+ * fastsv.h -- connected components of undirected graphs on MI355X (gfx950)
+ * with the FastSV method (Zhang, Azad, Hu, "FastSV: A Distributed-Memory
+ * Connected Component Algorithm with Fast Convergence", arXiv 1910.05971).
+ *
+ * Problem (Sec. 1, Sec. 2.1): an undirected graph G(V,E) with vertices
+ * 0..n-1.  Result: the parent vector f of Algorithm 2 at termination, in
+ * which every vertex points to the smallest vertex of its connected
+ * component (Sec. 3.4 and Appendix A); isolated vertices point to
+ * themselves.
+ *
+ * Method per iteration (Algorithm 3, Sec. 4.1), all on the GPU:
+ *   mngf = A (select2nd,min) gf, MIN-accumulated      -- SpMV (Sec. 4.1)
+ *   f[f_start[u]] <-min mngf[u]                       -- stochastic hooking (Sec. 3.2)
+ *   f[u] <-min mngf[u]                                -- aggressive hooking (Sec. 3.3)
+ *   f[u] <-min gf[u]                                  -- shortcutting
+ *   gf = f[f]; stop when gf is unchanged              -- early termination (Sec. 3.4)
+ * with the SpMV replaced by a push over the changed entries of gf when they
+ * are few (sparse frontier, Sec. 4.2 "Taking advantage of the sparsity").
+ * The default mode keeps separate read and write vectors (Sec. 2.4), so the
+ * iterates and the iteration count are deterministic and equal those of
+ * Algorithm 2.
+ *
+ * Conventions for every entry point
+ *   - Device pointers are plain hipMalloc'd (or torch-allocated) memory of
+ *     the current device of the context.  The caller owns all buffers; the
+ *     library keeps no pointer after a call returns.
+ *   - Return value: FASTSV_OK or a negative fastsv_status.  Argument errors
+ *     are detected before any launch; the output buffers are then untouched.
+ *     On FASTSV_EHIP the outputs are unspecified.
+ *   - A context is not thread-safe: use one per host thread.
+ */
+#ifndef FASTSV_H
+#define FASTSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FASTSV_OK = 0,
+    FASTSV_EINVAL = -1,        /* bad argument (null pointer, n < 0, bad options, workspace too small) */
+    FASTSV_ERANGE = -2,        /* validation found a column id outside [0,n) or a bad row_ptr */
+    FASTSV_EOVERFLOW = -3,     /* sizes do not fit the int32 layout */
+    FASTSV_ENOMEM = -4,        /* device or pinned host allocation failed */
+    FASTSV_EHIP = -5,          /* a HIP runtime call failed */
+    FASTSV_ENOTCONVERGED = -6, /* max_iters iterations ran without meeting the termination test */
+    FASTSV_EBUSY = -7          /* resource in use (serving: no free slot) */
+} fastsv_status;
+
+typedef struct fastsv_ctx fastsv_ctx;
+
+/* Solver options.  Zero-initialised options are NOT the defaults; start from
+ * fastsv_default_opts(). */
+typedef struct {
+    int32_t max_iters;      /* > 0: stop after this many iterations with FASTSV_ENOTCONVERGED and
+                               labels = f after that iteration; <= 0: no cap (the paper gives no
+                               iteration bound, Sec. 2.4) */
+    float frontier_tau;     /* sparse-frontier switch (Sec. 4.2): iteration k+1 pushes from the
+                               changed grandparents of iteration k when their total degree is
+                               below frontier_tau * nnz.  0: always dense SpMV; >= 1: sparse
+                               whenever possible (from iteration 2 on).  The labels and iterates
+                               do not depend on it. */
+    int32_t validate;       /* 1: check row_ptr (monotone, row_ptr[0] = 0, row_ptr[n] = nnz) and
+                               every column id on the device before solving (FASTSV_ERANGE) */
+    int32_t timing;         /* 1: time every kernel with HIP events on the call's stream
+                               (fills fastsv_stats.ms_hook / ms_gp) */
+    int32_t reserved[4];
+} fastsv_opts;
+
+#define FASTSV_TRACE_ITERS 64
+
+/* Per-call statistics (host memory, filled when the call returns). */
+typedef struct {
+    int32_t iterations;            /* iterations executed, including the confirming one */
+    int32_t dense_iterations;      /* iterations whose SpMV step was the dense pull */
+    int32_t sparse_iterations;     /* iterations that pushed from the changed grandparents */
+    int32_t num_tiles;             /* edge tiles of the dense kernel */
+    int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */
+    int64_t alg_bytes;             /* algorithmic bytes of all executed iterations (4 B per int32
+                                      read or written, each gather counted) */
+    double ms_total;               /* host wall time of the call */
+    int64_t changed[FASTSV_TRACE_ITERS];  /* entries of gf changed in iteration k (k < 64) */
+    int32_t sparse[FASTSV_TRACE_ITERS];   /* 1 if iteration k used the sparse push */
+    float ms_hook[FASTSV_TRACE_ITERS];    /* hooking kernel time of iteration k (opts.timing) */
+    float ms_gp[FASTSV_TRACE_ITERS];      /* grandparent/termination kernel time (opts.timing) */
+} fastsv_stats;
+
+/* Default options: no iteration cap, frontier_tau = 0.05, no validation, no timing. */
+fastsv_opts fastsv_default_opts(void);
+
+/* Create a context on HIP device `device` (allocates pinned host counters).
+ * *out is NULL on failure. */
+int fastsv_create(fastsv_ctx **out, int device);
+void fastsv_destroy(fastsv_ctx *ctx);
+
+const char *fastsv_strerror(int status);
+
+/*
+ * Workspace bytes needed by fastsv_cc_csr for a graph with n vertices and nnz
+ * stored entries: five int32[n] vectors (two parent buffers of the Jacobi
+ * pair, the MIN-accumulated mngf, the frontier list and its edge offsets),
+ * the dense kernel's tile table and counters.  Returns 0 for invalid sizes.
+ */
+size_t fastsv_workspace_bytes(int32_t n, int64_t nnz);
+
+/*
+ * Connected components of a graph in symmetric CSR form.
+ *
+ *   n          vertices (>= 0); n == 0 is a no-op
+ *   nnz        stored entries = row_ptr[n] (0 <= nnz < 2^31)
+ *   d_row_ptr  int32[n+1], nondecreasing, row_ptr[0] = 0, row_ptr[n] = nnz
+ *   d_col_idx  int32[nnz], ids in [0,n).  The matrix must be symmetric: the
+ *              method hooks only along stored entries (Alg. 3 multiplies by
+ *              the symmetric adjacency matrix); an entry stored in one
+ *              direction only does not connect its endpoints in both.
+ *              Self loops and duplicate entries are allowed.
+ *   d_labels   int32[n] output: labels[u] = min{w : w connected to u}
+ *              (on FASTSV_ENOTCONVERGED: f after max_iters iterations)
+ *   d_ws       workspace of at least fastsv_workspace_bytes(n, nnz) bytes,
+ *              256-byte aligned; NULL lets the context allocate and keep one
+ *   stream     HIP stream for all work; the call synchronises it once per
+ *              iteration (it reads the termination count) and returns after
+ *              the last kernel has finished
+ *   opts       NULL for defaults
+ *   stats      may be NULL
+ */
+int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
+                  const int32_t *d_col_idx, int32_t *d_labels, void *d_ws, size_t ws_bytes,
+                  hipStream_t stream, const fastsv_opts *opts, fastsv_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTSV_H */

@@ -1,1 +1,200 @@
-# placeholder
+"""ctypes binding of libfastsv.so (C ABI in include/fastsv.h).
+
+Argument marshalling only: torch tensors provide device memory and the HIP
+stream; every step of the method runs in the library's HIP kernels.  There is
+no fallback: if the library is missing or fails to load, every call raises.
+
+torch is imported before the library is loaded so that the library binds to
+the HIP runtime already in the process (the one torch uses for its tensors).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfastsv.so")
+
+TRACE_ITERS = 64
+
+FASTSV_OK = 0
+FASTSV_EINVAL = -1
+FASTSV_ERANGE = -2
+FASTSV_EOVERFLOW = -3
+FASTSV_ENOMEM = -4
+FASTSV_EHIP = -5
+FASTSV_ENOTCONVERGED = -6
+FASTSV_EBUSY = -7
+
+__all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "workspace_bytes", "load_library",
+           "FASTSV_OK", "FASTSV_EINVAL", "FASTSV_ERANGE", "FASTSV_EOVERFLOW", "FASTSV_ENOMEM",
+           "FASTSV_EHIP", "FASTSV_ENOTCONVERGED", "FASTSV_EBUSY"]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("frontier_tau", ctypes.c_float),
+                ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("dense_iterations", ctypes.c_int32),
+                ("sparse_iterations", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
+                ("frontier_edges", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
+                ("ms_total", ctypes.c_double),
+                ("changed", ctypes.c_int64 * TRACE_ITERS), ("sparse", ctypes.c_int32 * TRACE_ITERS),
+                ("ms_hook", ctypes.c_float * TRACE_ITERS), ("ms_gp", ctypes.c_float * TRACE_ITERS)]
+
+    def changed_list(self):
+        return [int(self.changed[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+    def sparse_list(self):
+        return [int(self.sparse[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+    def ms_hook_list(self):
+        return [float(self.ms_hook[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+    def ms_gp_list(self):
+        return [float(self.ms_gp[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+
+class FastSVError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_strerror(status)} ({status})")
+
+
+_lib = None
+_lock = threading.Lock()
+_ctx = {}
+
+
+def load_library():
+    """Load libfastsv.so (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with __graft_entry__.build()")
+            lib = ctypes.CDLL(LIB_PATH)
+            vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+            lib.fastsv_default_opts.restype = Opts
+            lib.fastsv_default_opts.argtypes = []
+            lib.fastsv_create.restype = ctypes.c_int
+            lib.fastsv_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+            lib.fastsv_destroy.restype = None
+            lib.fastsv_destroy.argtypes = [vp]
+            lib.fastsv_strerror.restype = ctypes.c_char_p
+            lib.fastsv_strerror.argtypes = [ctypes.c_int]
+            lib.fastsv_workspace_bytes.restype = sz
+            lib.fastsv_workspace_bytes.argtypes = [i32, i64]
+            lib.fastsv_cc_csr.restype = ctypes.c_int
+            lib.fastsv_cc_csr.argtypes = [vp, i32, i64, vp, vp, vp, vp, sz, vp,
+                                          ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+            _lib = lib
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load_library().fastsv_strerror(status).decode()
+    except Exception:  # pragma: no cover - only when the library itself is missing
+        return "unknown"
+
+
+def context(device: int):
+    """One library context per device (created on first use, kept for the process)."""
+    lib = load_library()
+    with _lock:
+        c = _ctx.get(device)
+        if c is None:
+            h = ctypes.c_void_p()
+            st = lib.fastsv_create(ctypes.byref(h), device)
+            if st != FASTSV_OK:
+                raise FastSVError(st, "fastsv_create")
+            c = _ctx[device] = h
+    return c
+
+
+def default_opts() -> Opts:
+    return load_library().fastsv_default_opts()
+
+
+def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None) -> Opts:
+    o = default_opts()
+    if max_iters is not None:
+        o.max_iters = int(max_iters)
+    if frontier_tau is not None:
+        o.frontier_tau = float(frontier_tau)
+    if validate is not None:
+        o.validate = int(bool(validate))
+    if timing is not None:
+        o.timing = int(bool(timing))
+    return o
+
+
+def workspace_bytes(n: int, nnz: int) -> int:
+    return int(load_library().fastsv_workspace_bytes(int(n), int(nnz)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_vec(t, name, n=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.int32:
+        raise TypeError(f"{name} must be int32")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements")
+
+
+def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
+           workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
+           max_iters=None, frontier_tau=None, validate=None, timing=None, check=True):
+    """Connected components of a symmetric int32 CSR graph resident on the GPU.
+
+    Returns (labels, stats); labels[u] is the smallest vertex of u's component.
+    With ``check=False`` the status is returned instead of raising:
+    (labels, stats, status)."""
+    _check_vec(row_ptr, "row_ptr")
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr needs n+1 >= 1 entries")
+    _check_vec(col, "col")
+    dev = row_ptr.device
+    if col.device != dev:
+        raise ValueError("row_ptr and col must be on the same device")
+    nnz = col.numel()
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    _check_vec(labels, "labels", n)
+    opts = make_opts(max_iters, frontier_tau, validate, timing)
+    if workspace is None:
+        wsb = workspace_bytes(n, nnz)
+        if wsb == 0:
+            raise ValueError("graph too large for the int32 layout")
+        workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) & ~255
+    ws_bytes = workspace.numel() - (aligned - base)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    stats = Stats()
+    lib = load_library()
+    st = lib.fastsv_cc_csr(context(dev.index if dev.index is not None else torch.cuda.current_device()),
+                           n, nnz, _ptr(row_ptr), _ptr(col), _ptr(labels),
+                           ctypes.c_void_p(aligned), ws_bytes, ctypes.c_void_p(s.cuda_stream),
+                           ctypes.byref(opts), ctypes.byref(stats))
+    if not check:
+        return labels, stats, st
+    if st != FASTSV_OK:
+        raise FastSVError(st, "fastsv_cc_csr")
+    return labels, stats

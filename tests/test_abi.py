@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every function include/*.h declares
+(no GPU needed; no compute call is made)."""
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(fastsv_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ("fastsv_create", "fastsv_destroy", "fastsv_cc_csr", "fastsv_workspace_bytes",
+                     "fastsv_strerror", "fastsv_default_opts"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1910_05971_amd import binding
+    lib = binding.load_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_defaults_and_sizes():
+    from paper_1910_05971_amd import binding
+    o = binding.default_opts()
+    assert o.max_iters == 0 and abs(o.frontier_tau - 0.05) < 1e-7 and o.validate == 0
+    assert binding.workspace_bytes(-1, 0) == 0
+    assert binding.workspace_bytes(10, 2**31) == 0
+    a = binding.workspace_bytes(1000, 5000)
+    b = binding.workspace_bytes(2000, 5000)
+    assert 0 < a < b
+    # five int32[n] vectors at least
+    assert binding.workspace_bytes(1 << 20, 0) >= 5 * 4 * (1 << 20)
+    lib = binding.load_library()
+    assert lib.fastsv_strerror(0) == b"ok"
+    assert b"max_iters" in lib.fastsv_strerror(-6)

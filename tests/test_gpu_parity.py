@@ -1,0 +1,199 @@
+"""HIP path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Labels are compared element by element (bit-exact: integer work).  In the
+default Jacobi mode the whole trajectory is deterministic (Sec. 2.4), so the
+iteration count, the per-iteration count of changed grandparents and, on
+moderate graphs, every iterate f_k (read back by capping max_iters at k) must
+equal Algorithm 2's.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle_pins as P
+from paper_1910_05971_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(g):
+    return (torch.from_numpy(np.ascontiguousarray(g.row_ptr)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(g.col)).cuda())
+
+
+def solve(rp, col, **kw):
+    import paper_1910_05971_amd as fs
+    labels, stats = fs.cc_csr(rp, col, **kw)
+    torch.cuda.synchronize()
+    return labels.cpu().numpy(), stats
+
+
+def check_graph(g, taus=(0.05,), trajectory=False, oracle_alg2=True):
+    _say(f"[gpu] {g.name} n={g.n} nnz={g.nnz}")
+    rp, col = to_dev(g)
+    want = O.uf_labels(g.n, g.row_ptr, g.col)
+    ref = O.fastsv_alg2(g.n, g.row_ptr, g.col, trace_cap=256 if trajectory else 0) if oracle_alg2 else None
+    for tau in taus:
+        got, st = solve(rp, col, frontier_tau=tau, validate=True)
+        assert np.array_equal(got, want), f"{g.name} tau={tau}: labels differ at {np.flatnonzero(got != want)[:10]}"
+        if ref is not None:
+            assert st.iterations == ref.iterations, (g.name, tau, st.iterations, ref.iterations)
+            k = min(ref.iterations, 64)
+            if trajectory:
+                assert st.changed_list()[:k] == ref.changed[:k].tolist(), (g.name, tau)
+    if trajectory and ref is not None:
+        for k in range(1, ref.iterations + 1):
+            for tau in taus:
+                got, st = solve(rp, col, frontier_tau=tau, max_iters=k)
+                assert np.array_equal(got, ref.trace[k - 1]), f"{g.name} tau={tau}: f_{k} differs"
+    return ref
+
+
+def test_exhaustive_small_graphs(gpu_ok):
+    # every graph on 5 vertices, dense and sparse-always
+    n = 5
+    pairs_all = list(itertools.combinations(range(n), 2))
+    _say("[gpu] exhaustive n=5")
+    for mask in range(1 << len(pairs_all)):
+        pairs = [p for i, p in enumerate(pairs_all) if mask >> i & 1]
+        rp_h, col_h = P.csr_from_pairs(n, pairs)
+        want = P.py_bfs_labels(n, pairs)
+        ref = O.fastsv_alg2(n, rp_h, col_h, trace_cap=16)
+        rp, col = torch.from_numpy(rp_h).cuda(), torch.from_numpy(col_h).cuda()
+        for tau in (0.0, 1.0):
+            got, st = solve(rp, col, frontier_tau=tau)
+            assert np.array_equal(got, want), (pairs, tau)
+            assert st.iterations == ref.iterations, (pairs, tau)
+            assert st.changed_list() == ref.changed.tolist(), (pairs, tau)
+
+
+def test_golden_and_closed_forms(gpu_ok):
+    import json
+    import os
+    for fname in sorted(os.listdir(P.GOLDEN)):
+        ex = json.load(open(os.path.join(P.GOLDEN, fname)))
+        rp_h, col_h = P.csr_from_pairs(ex["n"], ex["edges"])
+        rp, col = torch.from_numpy(rp_h).cuda(), torch.from_numpy(col_h).cuda()
+        for tau in (0.0, 1.0):
+            for k, fk in enumerate(ex["trajectory"], start=1):
+                got, _ = solve(rp, col, frontier_tau=tau, max_iters=k)
+                assert got.tolist() == fk, (fname, tau, k)
+    for n in (1, 2, 3, 17, 64, 1000, 4097):
+        rp_h, col_h = P.csr_from_pairs(n, [(u, u + 1) for u in range(n - 1)])
+        rp, col = torch.from_numpy(rp_h).cuda(), torch.from_numpy(col_h).cuda()
+        K = P.path_iterations(n)
+        for tau in (0.0, 1.0):
+            for k in range(1, K + 1):
+                got, st = solve(rp, col, frontier_tau=tau, max_iters=k)
+                assert np.array_equal(got, P.path_closed_form(n, k)), (n, tau, k)
+            _, st = solve(rp, col, frontier_tau=tau)
+            assert st.iterations == K
+
+
+def test_random_trajectories(gpu_ok):
+    graphs = [gg.er(3000, 3500, seed=41), gg.er(20000, 80000, seed=42), gg.rmat(14, 16, seed=43),
+              gg.grid(100, 120, 0.55, seed=44), gg.rmat(12, 4, seed=45)]
+    for g in graphs:
+        check_graph(g, taus=(0.0, 0.05, 1.0), trajectory=True)
+
+
+def test_edge_cases(gpu_ok):
+    # empty vertex set
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    col = torch.zeros(0, dtype=torch.int32, device="cuda")
+    got, st = solve(rp, col)
+    assert got.shape == (0,) and st.iterations == 0
+    # edgeless
+    for n in (1, 5, 100000):
+        rp = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+        got, st = solve(rp, col)
+        assert np.array_equal(got, np.arange(n)) and st.iterations == 1
+    # self loops and duplicates only
+    pairs = [(0, 0), (3, 3), (1, 2), (1, 2), (2, 1)]
+    rp_h, col_h = P.csr_from_pairs(6, pairs)
+    got, _ = solve(torch.from_numpy(rp_h).cuda(), torch.from_numpy(col_h).cuda())
+    assert got.tolist() == [0, 1, 1, 3, 4, 5]
+
+
+def test_hub_rows_and_ragged_tiles(gpu_ok):
+    rng = np.random.default_rng(5)
+    # one hub spanning hundreds of tiles, plus degree-15/16/17 rows around lane boundaries
+    n = 300000
+    hub = 123457
+    pairs = [(hub, int(v)) for v in rng.choice(n, 150000, replace=False) if v != hub]
+    for d in (15, 16, 17, 63, 64, 65, 1023, 1024, 1025):
+        c = int(rng.integers(0, n))
+        pairs += [(c, int(v)) for v in rng.integers(0, n, d) if v != c]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    g = gg.Graph("hub_ragged", n, rp_h, col_h, len(pairs))
+    check_graph(g, taus=(0.0, 1.0), trajectory=True)
+
+
+def test_sparse_rows_wide_windows(gpu_ok):
+    # a few edges spread over a huge id range: tiles span far more rows than
+    # the LDS window holds
+    rng = np.random.default_rng(7)
+    n = 3_000_000
+    ids = np.sort(rng.choice(n, 4000, replace=False))
+    pairs = [(int(ids[i]), int(ids[i + 1])) for i in range(0, 3999, 2)]
+    pairs += [(int(ids[i]), int(ids[(i * 7) % 4000])) for i in range(0, 4000, 3)]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    g = gg.Graph("wide_windows", n, rp_h, col_h, len(pairs))
+    check_graph(g, taus=(0.0, 1.0), trajectory=True)
+
+
+def test_validation_rejects_bad_graph(gpu_ok):
+    import paper_1910_05971_amd as fs
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
+    col = torch.tensor([1, 7], dtype=torch.int32, device="cuda")  # 7 is out of range
+    labels = torch.full((2,), -5, dtype=torch.int32, device="cuda")
+    _, _, st = fs.cc_csr(rp, col, labels=labels, validate=True, check=False)
+    assert st == fs.FASTSV_ERANGE
+    assert labels.cpu().tolist() == [-5, -5]  # untouched
+    rp_bad = torch.tensor([0, 2, 1], dtype=torch.int32, device="cuda")
+    _, _, st = fs.cc_csr(rp_bad, torch.tensor([1], dtype=torch.int32, device="cuda"), validate=True,
+                         check=False)
+    assert st == fs.FASTSV_ERANGE
+
+
+def test_deterministic_repeats(gpu_ok):
+    g = gg.rmat(15, 16, seed=46)
+    rp, col = to_dev(g)
+    outs = set()
+    for _ in range(5):
+        got, st = solve(rp, col, max_iters=2)
+        outs.add(got.tobytes())
+    assert len(outs) == 1
+
+
+def test_config_c1(gpu_ok):
+    g = gg.c1_er()
+    check_graph(g, taus=(0.0, 0.05, 1.0), trajectory=True)
+
+
+@pytest.mark.slow
+def test_config_c3_grid(gpu_ok):
+    g = gg.c3_grid()
+    check_graph(g, taus=(0.05,), trajectory=False, oracle_alg2=True)
+
+
+@pytest.mark.slow
+def test_config_c2_rmat(gpu_ok):
+    g = gg.c2_rmat()
+    _say(f"[gpu] C2 n={g.n} nnz={g.nnz}")
+    rp, col = to_dev(g)
+    want = O.uf_labels(g.n, g.row_ptr, g.col)
+    for tau in (0.0, 0.05):
+        got, st = solve(rp, col, frontier_tau=tau)
+        assert np.array_equal(got, want), f"C2 tau={tau}"
+        _say(f"[gpu] C2 tau={tau} iterations={st.iterations} changed={st.changed_list()}")
+    O.check_final(got, g.row_ptr, g.col)
