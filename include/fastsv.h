@@ -69,7 +69,13 @@ typedef struct {
                                every column id on the device before solving (FASTSV_ERANGE) */
     int32_t timing;         /* 1: time every kernel with HIP events on the call's stream
                                (fills fastsv_stats.ms_hook / ms_gp) */
-    int32_t reserved[4];
+    int32_t blocked;        /* column-blocked dense SpMV passes (need rows sorted by column id;
+                               otherwise the plain pass runs): 1 use them; 0 or -1 (automatic,
+                               the default, currently equal to 0) do not.  Same iterates either way. */
+    int32_t block_shift;    /* log2 of the column-block width in vertices; 0 = automatic (2^19,
+                               widened so that there are at most 64 blocks).  4..30 otherwise, and
+                               the graph must then have at most 64 blocks. */
+    int32_t reserved[2];
 } fastsv_opts;
 
 #define FASTSV_TRACE_ITERS 64
@@ -80,6 +86,8 @@ typedef struct {
     int32_t dense_iterations;      /* iterations whose SpMV step was the dense pull */
     int32_t sparse_iterations;     /* iterations that pushed from the changed grandparents */
     int32_t num_tiles;             /* edge tiles of the dense kernel */
+    int32_t blocked_prepared;      /* 1 if the column-blocked layout was built in this call */
+    int32_t blocked_iterations;    /* dense iterations that ran the column-blocked passes */
     int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */
     int64_t alg_bytes;             /* algorithmic bytes of all executed iterations (4 B per int32
                                       read or written, each gather counted) */
@@ -90,7 +98,8 @@ typedef struct {
     float ms_gp[FASTSV_TRACE_ITERS];      /* grandparent/termination kernel time (opts.timing) */
 } fastsv_stats;
 
-/* Default options: no iteration cap, frontier_tau = 0.05, no validation, no timing. */
+/* Default options: no iteration cap, frontier_tau = 0.05, no validation, no timing,
+ * automatic column blocking. */
 fastsv_opts fastsv_default_opts(void);
 
 /* Create a context on HIP device `device` (allocates pinned host counters).
@@ -104,9 +113,15 @@ const char *fastsv_strerror(int status);
  * Workspace bytes needed by fastsv_cc_csr for a graph with n vertices and nnz
  * stored entries: five int32[n] vectors (two parent buffers of the Jacobi
  * pair, the MIN-accumulated mngf, the frontier list and its edge offsets),
- * the dense kernel's tile table and counters.  Returns 0 for invalid sizes.
+ * the dense kernel's tile table and counters.  With blocked = 1 the
+ * column-blocked copy of the matrix is added (about 3 int32 per stored entry).
+ * Returns 0 for invalid sizes.
  */
 size_t fastsv_workspace_bytes(int32_t n, int64_t nnz);
+
+/* Workspace bytes for the given options (blocked = 1 or block_shift change the
+ * layout); returns 0 for invalid sizes or options. */
+size_t fastsv_workspace_bytes_opts(int32_t n, int64_t nnz, const fastsv_opts *opts);
 
 /*
  * Connected components of a graph in symmetric CSR form.
@@ -121,7 +136,7 @@ size_t fastsv_workspace_bytes(int32_t n, int64_t nnz);
  *              Self loops and duplicate entries are allowed.
  *   d_labels   int32[n] output: labels[u] = min{w : w connected to u}
  *              (on FASTSV_ENOTCONVERGED: f after max_iters iterations)
- *   d_ws       workspace of at least fastsv_workspace_bytes(n, nnz) bytes,
+ *   d_ws       workspace of at least fastsv_workspace_bytes_opts(n, nnz, opts) bytes,
  *              256-byte aligned; NULL lets the context allocate and keep one
  *   stream     HIP stream for all work; the call synchronises it once per
  *              iteration (it reads the termination count) and returns after

@@ -101,11 +101,11 @@ class Oracle:
             raise MemoryError("oracle allocation failed")
         return out
 
-    def _run(self, fn, n, row_ptr, col, max_iters, trace_cap, before=(), after=()):
+    def _run(self, fn, n, row_ptr, col, max_iters, trace_cap, before=(), after=(), record_f=True):
         row_ptr, col = _csr(row_ptr, col)
         f = np.empty(n, dtype=np.int32)
         cap = int(trace_cap)
-        tr = np.empty((cap, n), dtype=np.int32) if cap > 0 else None
+        tr = np.empty((cap, n), dtype=np.int32) if cap > 0 and record_f else None
         ch = np.empty(max(cap, 1), dtype=np.int64)
         it = fn(n, _p(row_ptr), _p(col), *before, int(max_iters), *after, _p(f), _p(tr), _p(ch), cap)
         if it == -2:
@@ -113,8 +113,9 @@ class Oracle:
         k = min(cap, max_iters if it == -1 else it) if cap > 0 else 0
         return Result(f, int(it), tr[:k] if tr is not None else None, ch[:k] if cap > 0 else None)
 
-    def fastsv_alg2(self, n, row_ptr, col, max_iters=0, trace_cap=0) -> Result:
-        return self._run(self.lib.oracle_fastsv_alg2, n, row_ptr, col, max_iters, trace_cap)
+    def fastsv_alg2(self, n, row_ptr, col, max_iters=0, trace_cap=0, record_f=True) -> Result:
+        """record_f=False keeps only the per-iteration changed counts."""
+        return self._run(self.lib.oracle_fastsv_alg2, n, row_ptr, col, max_iters, trace_cap, record_f=record_f)
 
     def fastsv_alg3(self, n, row_ptr, col, max_iters=0, trace_cap=0, f_init=None) -> Result:
         fi = None if f_init is None else np.ascontiguousarray(f_init, dtype=np.int32)
@@ -156,8 +157,8 @@ def bfs_labels(n, row_ptr, col):
     return default().bfs_labels(n, row_ptr, col)
 
 
-def fastsv_alg2(n, row_ptr, col, max_iters=0, trace_cap=0):
-    return default().fastsv_alg2(n, row_ptr, col, max_iters, trace_cap)
+def fastsv_alg2(n, row_ptr, col, max_iters=0, trace_cap=0, record_f=True):
+    return default().fastsv_alg2(n, row_ptr, col, max_iters, trace_cap, record_f)
 
 
 def fastsv_alg3(n, row_ptr, col, max_iters=0, trace_cap=0, f_init=None):

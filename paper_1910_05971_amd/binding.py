@@ -37,12 +37,14 @@ __all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "workspace_bytes", "load_li
 class Opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("frontier_tau", ctypes.c_float),
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("blocked", ctypes.c_int32), ("block_shift", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("dense_iterations", ctypes.c_int32),
                 ("sparse_iterations", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
+                ("blocked_prepared", ctypes.c_int32), ("blocked_iterations", ctypes.c_int32),
                 ("frontier_edges", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
                 ("ms_total", ctypes.c_double),
                 ("changed", ctypes.c_int64 * TRACE_ITERS), ("sparse", ctypes.c_int32 * TRACE_ITERS),
@@ -91,6 +93,8 @@ def load_library():
             lib.fastsv_strerror.argtypes = [ctypes.c_int]
             lib.fastsv_workspace_bytes.restype = sz
             lib.fastsv_workspace_bytes.argtypes = [i32, i64]
+            lib.fastsv_workspace_bytes_opts.restype = sz
+            lib.fastsv_workspace_bytes_opts.argtypes = [i32, i64, ctypes.POINTER(Opts)]
             lib.fastsv_cc_csr.restype = ctypes.c_int
             lib.fastsv_cc_csr.argtypes = [vp, i32, i64, vp, vp, vp, vp, sz, vp,
                                           ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
@@ -123,8 +127,14 @@ def default_opts() -> Opts:
     return load_library().fastsv_default_opts()
 
 
-def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None) -> Opts:
+def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None,
+              block_shift=None) -> Opts:
+    """blocked: None/"auto" -> automatic, False -> never, True -> always."""
     o = default_opts()
+    if blocked is not None and blocked != "auto":
+        o.blocked = 1 if blocked else 0
+    if block_shift is not None:
+        o.block_shift = int(block_shift)
     if max_iters is not None:
         o.max_iters = int(max_iters)
     if frontier_tau is not None:
@@ -136,8 +146,10 @@ def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None) -> 
     return o
 
 
-def workspace_bytes(n: int, nnz: int) -> int:
-    return int(load_library().fastsv_workspace_bytes(int(n), int(nnz)))
+def workspace_bytes(n: int, nnz: int, opts: Opts | None = None) -> int:
+    if opts is None:
+        return int(load_library().fastsv_workspace_bytes(int(n), int(nnz)))
+    return int(load_library().fastsv_workspace_bytes_opts(int(n), int(nnz), ctypes.byref(opts)))
 
 
 def _ptr(t):
@@ -159,7 +171,8 @@ def _check_vec(t, name, n=None):
 
 def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
-           max_iters=None, frontier_tau=None, validate=None, timing=None, check=True):
+           max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None, block_shift=None,
+           check=True):
     """Connected components of a symmetric int32 CSR graph resident on the GPU.
 
     Returns (labels, stats); labels[u] is the smallest vertex of u's component.
@@ -177,11 +190,11 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift)
     if workspace is None:
-        wsb = workspace_bytes(n, nnz)
+        wsb = workspace_bytes(n, nnz, opts)
         if wsb == 0:
-            raise ValueError("graph too large for the int32 layout")
+            raise ValueError("sizes do not fit the int32 layout, or invalid options")
         workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=dev)
     base = workspace.data_ptr()
     aligned = (base + 255) & ~255

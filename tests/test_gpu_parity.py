@@ -31,29 +31,32 @@ def to_dev(g):
 
 
 def solve(rp, col, **kw):
+    """Solve; a capped run (max_iters) may end with FASTSV_ENOTCONVERGED and
+    then returns f after max_iters iterations."""
     import paper_1910_05971_amd as fs
-    labels, stats = fs.cc_csr(rp, col, **kw)
+    labels, stats, st = fs.cc_csr(rp, col, check=False, **kw)
     torch.cuda.synchronize()
+    ok = (fs.FASTSV_OK, fs.FASTSV_ENOTCONVERGED) if kw.get("max_iters") else (fs.FASTSV_OK,)
+    assert st in ok, f"status {st}"
     return labels.cpu().numpy(), stats
 
 
-def check_graph(g, taus=(0.05,), trajectory=False, oracle_alg2=True):
-    _say(f"[gpu] {g.name} n={g.n} nnz={g.nnz}")
+def check_graph(g, taus=(0.05,), trajectory=False, oracle_alg2=True, **kw):
+    _say(f"[gpu] {g.name} n={g.n} nnz={g.nnz} {kw}")
     rp, col = to_dev(g)
     want = O.uf_labels(g.n, g.row_ptr, g.col)
-    ref = O.fastsv_alg2(g.n, g.row_ptr, g.col, trace_cap=256 if trajectory else 0) if oracle_alg2 else None
+    ref = O.fastsv_alg2(g.n, g.row_ptr, g.col, trace_cap=256, record_f=trajectory) if oracle_alg2 else None
     for tau in taus:
-        got, st = solve(rp, col, frontier_tau=tau, validate=True)
+        got, st = solve(rp, col, frontier_tau=tau, validate=True, **kw)
         assert np.array_equal(got, want), f"{g.name} tau={tau}: labels differ at {np.flatnonzero(got != want)[:10]}"
         if ref is not None:
             assert st.iterations == ref.iterations, (g.name, tau, st.iterations, ref.iterations)
             k = min(ref.iterations, 64)
-            if trajectory:
-                assert st.changed_list()[:k] == ref.changed[:k].tolist(), (g.name, tau)
+            assert st.changed_list()[:k] == ref.changed[:k].tolist(), (g.name, tau)
     if trajectory and ref is not None:
         for k in range(1, ref.iterations + 1):
             for tau in taus:
-                got, st = solve(rp, col, frontier_tau=tau, max_iters=k)
+                got, st = solve(rp, col, frontier_tau=tau, max_iters=k, **kw)
                 assert np.array_equal(got, ref.trace[k - 1]), f"{g.name} tau={tau}: f_{k} differs"
     return ref
 
@@ -151,6 +154,33 @@ def test_sparse_rows_wide_windows(gpu_ok):
     check_graph(g, taus=(0.0, 1.0), trajectory=True)
 
 
+def test_blocked_passes_trajectories(gpu_ok):
+    # column-blocked dense passes forced on moderate graphs with many blocks
+    import paper_1910_05971_amd as fs
+    graphs = [(gg.rmat(14, 16, seed=51), 8), (gg.er(30000, 120000, seed=52), 9),
+              (gg.grid(120, 150, 0.6, seed=53), 9), (gg.rmat(16, 8, seed=54), 10)]
+    for g, shift in graphs:
+        ref = check_graph(g, taus=(0.0, 0.05), trajectory=True, blocked=True, block_shift=shift)
+        rp, col = to_dev(g)
+        _, st = solve(rp, col, frontier_tau=0.0, blocked=True, block_shift=shift)
+        assert st.blocked_prepared == 1
+        assert st.blocked_iterations == max(0, ref.iterations - 1), (g.name, st.blocked_iterations)
+
+
+def test_blocked_unsorted_rows_fall_back(gpu_ok):
+    g = gg.er(20000, 60000, seed=55)
+    rng = np.random.default_rng(3)
+    col = g.col.copy()
+    for u in range(g.n):
+        a, b = g.row_ptr[u], g.row_ptr[u + 1]
+        col[a:b] = rng.permutation(col[a:b])
+    g2 = gg.Graph("er_unsorted", g.n, g.row_ptr, col, g.m_eff)
+    check_graph(g2, taus=(0.0,), trajectory=True, blocked=True, block_shift=9)
+    rp_d, col_d = to_dev(g2)
+    _, st = solve(rp_d, col_d, frontier_tau=0.0, blocked=True, block_shift=9)
+    assert st.blocked_prepared == 1 and st.blocked_iterations == 0
+
+
 def test_validation_rejects_bad_graph(gpu_ok):
     import paper_1910_05971_amd as fs
     rp = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
@@ -192,8 +222,9 @@ def test_config_c2_rmat(gpu_ok):
     _say(f"[gpu] C2 n={g.n} nnz={g.nnz}")
     rp, col = to_dev(g)
     want = O.uf_labels(g.n, g.row_ptr, g.col)
-    for tau in (0.0, 0.05):
-        got, st = solve(rp, col, frontier_tau=tau)
-        assert np.array_equal(got, want), f"C2 tau={tau}"
-        _say(f"[gpu] C2 tau={tau} iterations={st.iterations} changed={st.changed_list()}")
+    for tau, blocked in ((0.0, False), (0.05, None), (0.05, True)):
+        got, st = solve(rp, col, frontier_tau=tau, blocked=blocked)
+        assert np.array_equal(got, want), f"C2 tau={tau} blocked={blocked}"
+        _say(f"[gpu] C2 tau={tau} blocked={blocked} iterations={st.iterations} changed={st.changed_list()} "
+             f"blocked_iterations={st.blocked_iterations}")
     O.check_final(got, g.row_ptr, g.col)
