@@ -148,6 +148,48 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_
                   const int32_t *d_col_idx, int32_t *d_labels, void *d_ws, size_t ws_bytes,
                   hipStream_t stream, const fastsv_opts *opts, fastsv_stats *stats);
 
+/*
+ * Edge-list entry (the problem statement of Sec. 1 and the edge form of
+ * Algorithm 2): n vertices, m undirected edges given once each as
+ * (d_src[i], d_dst[i]) in either orientation; self loops and repeats are
+ * allowed.  The library builds the symmetric CSR on the device (edge (u,v)
+ * stored in both rows) and then runs fastsv_cc_csr's loop on it, so labels,
+ * iterates and iteration count equal those of the CSR entry on that matrix.
+ *   m          0 <= 2m < 2^31
+ *   d_ws       at least fastsv_edges_workspace_bytes(n, m) bytes (or NULL)
+ *   opts.blocked / block_shift are ignored (the built rows are unsorted).
+ */
+size_t fastsv_edges_workspace_bytes(int32_t n, int64_t m);
+int fastsv_cc_edges(fastsv_ctx *ctx, int32_t n, int64_t m, const int32_t *d_src, const int32_t *d_dst,
+                    int32_t *d_labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                    const fastsv_opts *opts, fastsv_stats *stats);
+
+/*
+ * Batch of independent graphs solved in one pass of launches.  Graph g owns
+ * the vertices [vtx_off[g], vtx_off[g+1]) of the concatenation and the entries
+ * [edge_off[g], edge_off[g+1]); row_ptr is global over the concatenation
+ * (row_ptr[vtx_off[g]] = edge_off[g]) and column ids are LOCAL to the graph
+ * (0 .. n_g-1).  Each graph is solved exactly as alone: the batch runs
+ * Algorithm 3 on the block-diagonal union with every vertex keeping a global
+ * id, so no hook ever crosses graphs and every graph's iterates are those of
+ * its solo run, shifted by vtx_off[g].
+ *   num_graphs  G >= 0; total_n = vtx_off[G] < 2^31; total_nnz = edge_off[G] < 2^31
+ *   d_vtx_off, d_edge_off  int32[G+1] device arrays, nondecreasing, starting at 0
+ *   d_labels    int32[total_n] output, LOCAL ids: labels[vtx_off[g] + u] =
+ *               smallest local vertex of u's component in graph g
+ *   d_iters     int32[G] output: iterations graph g needs alone (-1 if it had
+ *               not converged when max_iters stopped the batch; 0 for a graph
+ *               without vertices)
+ *   d_ws        at least fastsv_batch_workspace_bytes(total_n, total_nnz) bytes (or NULL)
+ *   opts.validate also checks the offsets against row_ptr and the local ids.
+ * The call returns after the last kernel has finished.
+ */
+size_t fastsv_batch_workspace_bytes(int32_t total_n, int64_t total_nnz);
+int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, int64_t total_nnz,
+                        const int32_t *d_vtx_off, const int32_t *d_edge_off, const int32_t *d_row_ptr,
+                        const int32_t *d_col_idx, int32_t *d_labels, int32_t *d_iters, void *d_ws,
+                        size_t ws_bytes, hipStream_t stream, const fastsv_opts *opts, fastsv_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,8 @@ FASTSV_EHIP = -5
 FASTSV_ENOTCONVERGED = -6
 FASTSV_EBUSY = -7
 
-__all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "workspace_bytes", "load_library",
+__all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "cc_edges", "cc_batch_csr", "workspace_bytes",
+           "load_library",
            "FASTSV_OK", "FASTSV_EINVAL", "FASTSV_ERANGE", "FASTSV_EOVERFLOW", "FASTSV_ENOMEM",
            "FASTSV_EHIP", "FASTSV_ENOTCONVERGED", "FASTSV_EBUSY"]
 
@@ -98,6 +99,16 @@ def load_library():
             lib.fastsv_cc_csr.restype = ctypes.c_int
             lib.fastsv_cc_csr.argtypes = [vp, i32, i64, vp, vp, vp, vp, sz, vp,
                                           ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+            lib.fastsv_edges_workspace_bytes.restype = sz
+            lib.fastsv_edges_workspace_bytes.argtypes = [i32, i64]
+            lib.fastsv_cc_edges.restype = ctypes.c_int
+            lib.fastsv_cc_edges.argtypes = [vp, i32, i64, vp, vp, vp, vp, sz, vp,
+                                            ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+            lib.fastsv_batch_workspace_bytes.restype = sz
+            lib.fastsv_batch_workspace_bytes.argtypes = [i32, i64]
+            lib.fastsv_cc_batch_csr.restype = ctypes.c_int
+            lib.fastsv_cc_batch_csr.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp,
+                                                ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
             _lib = lib
     return _lib
 
@@ -211,3 +222,77 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     if st != FASTSV_OK:
         raise FastSVError(st, "fastsv_cc_csr")
     return labels, stats
+
+
+def _workspace(nbytes, dev, workspace):
+    if workspace is None:
+        if nbytes == 0:
+            raise ValueError("sizes do not fit the int32 layout, or invalid options")
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) & ~255
+    return workspace, ctypes.c_void_p(aligned), workspace.numel() - (aligned - base)
+
+
+def _dev_index(dev):
+    return dev.index if dev.index is not None else torch.cuda.current_device()
+
+
+def cc_edges(n: int, src: torch.Tensor, dst: torch.Tensor, *, labels=None, workspace=None, stream=None,
+             max_iters=None, frontier_tau=None, validate=None, timing=None, check=True):
+    """Connected components from an undirected edge list (each edge once, any
+    orientation).  Returns (labels, stats)."""
+    _check_vec(src, "src")
+    _check_vec(dst, "dst", src.numel())
+    dev = src.device
+    m = src.numel()
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    _check_vec(labels, "labels", n)
+    opts = make_opts(max_iters, frontier_tau, validate, timing)
+    lib = load_library()
+    workspace, ws, wsb = _workspace(int(lib.fastsv_edges_workspace_bytes(int(n), int(m))), dev, workspace)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    stats = Stats()
+    st = lib.fastsv_cc_edges(context(_dev_index(dev)), int(n), int(m), _ptr(src), _ptr(dst), _ptr(labels), ws, wsb,
+                             ctypes.c_void_p(s.cuda_stream), ctypes.byref(opts), ctypes.byref(stats))
+    if not check:
+        return labels, stats, st
+    if st != FASTSV_OK:
+        raise FastSVError(st, "fastsv_cc_edges")
+    return labels, stats
+
+
+def cc_batch_csr(vtx_off: torch.Tensor, edge_off: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, *,
+                 labels=None, iters=None, workspace=None, stream=None, max_iters=None, frontier_tau=None,
+                 validate=None, timing=None, check=True):
+    """Many graphs in one call.  row_ptr is global over the concatenation,
+    column ids are local to each graph.  Returns (labels in local ids,
+    per-graph iteration counts, stats)."""
+    for t, name in ((vtx_off, "vtx_off"), (edge_off, "edge_off"), (row_ptr, "row_ptr"), (col, "col")):
+        _check_vec(t, name)
+    g = vtx_off.numel() - 1
+    if g < 0 or edge_off.numel() != g + 1:
+        raise ValueError("vtx_off and edge_off need G+1 entries")
+    dev = row_ptr.device
+    total_n = row_ptr.numel() - 1
+    total_nnz = col.numel()
+    if labels is None:
+        labels = torch.empty(total_n, dtype=torch.int32, device=dev)
+    if iters is None:
+        iters = torch.empty(max(g, 1), dtype=torch.int32, device=dev)
+    _check_vec(labels, "labels", total_n)
+    opts = make_opts(max_iters, frontier_tau, validate, timing)
+    lib = load_library()
+    workspace, ws, wsb = _workspace(int(lib.fastsv_batch_workspace_bytes(int(total_n), int(total_nnz))), dev,
+                                    workspace)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    stats = Stats()
+    st = lib.fastsv_cc_batch_csr(context(_dev_index(dev)), int(g), int(total_n), int(total_nnz), _ptr(vtx_off),
+                                 _ptr(edge_off), _ptr(row_ptr), _ptr(col), _ptr(labels), _ptr(iters), ws, wsb,
+                                 ctypes.c_void_p(s.cuda_stream), ctypes.byref(opts), ctypes.byref(stats))
+    if not check:
+        return labels, iters[:g], stats, st
+    if st != FASTSV_OK:
+        raise FastSVError(st, "fastsv_cc_batch_csr")
+    return labels, iters[:g], stats

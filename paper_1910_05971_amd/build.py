@@ -52,7 +52,7 @@ def build_hip():
     os.makedirs(LIBDIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = _atomic_out(HIP_LIB)
-    _run([hipcc, *HIP_FLAGS, "-I", INCLUDE, *[os.path.join(CSRC, s) for s in HIP_SOURCES],
+    _run([hipcc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, *[os.path.join(CSRC, s) for s in HIP_SOURCES],
           "-o", tmp])
     os.replace(tmp, HIP_LIB)
 

@@ -1,0 +1,92 @@
+// Internal interface of the FastSV library (not part of the public C ABI):
+// shared layout types, kernel geometry and host-side launch wrappers used by
+// the solver entry points and by the serving scheduler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fsv {
+
+constexpr int kWave = 64;
+
+// ---- dense hook kernel geometry ----
+constexpr int kPerLane = 16;                  // consecutive entries per lane
+constexpr int kTileEntries = kWave * kPerLane; // entries per wave tile
+constexpr int kHookWaves = 4;                 // waves per workgroup
+constexpr int kRowWin = 512;                  // row_ptr window held in LDS per wave
+
+// ---- grandparent kernel geometry ----
+constexpr int kGpThreads = 1024;
+constexpr int kGpPerThread = 4;
+constexpr int kGpBlockVerts = kGpThreads * kGpPerThread;
+
+// ---- sparse push kernel geometry ----
+constexpr int kPushThreads = 256;
+constexpr int kPushSlots = 2048;              // edge slots per workgroup
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+struct Tile {
+    int e0, e1;      // entry range [e0, e1)
+    int r_lo, r_hi;  // rows containing entries e0 and e1-1
+};
+
+// Per-iteration counters written by the grandparent pass (two slots, used
+// alternately by consecutive iterations).
+struct IterCounters {
+    // high 32 bits: entries of gf that changed (termination test; they form the
+    // frontier list), low 32 bits: their total degree
+    unsigned long long packed;
+    unsigned long long pad;
+};
+
+struct Counters {
+    IterCounters it[2];
+    int status;
+    int pad[7];
+};
+
+constexpr int kMaxBlocks = 64;
+
+// Exclusive-scan geometry.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+// Per-block description of the column-blocked layout.
+struct CbInfo {
+    int cbb[kMaxBlocks + 1];   // aligned entry base of each block; cbb[nblk] = padded total
+    int len[kMaxBlocks];       // entries of each block
+    int sbb[kMaxBlocks + 1];   // segment base of each block; sbb[nblk] = S
+    int tb[kMaxBlocks + 1];    // phase tile base of each block; tb[nblk] = total phase tiles
+    int flags;                 // bit 0: some row is not sorted
+    int pad[3];
+};
+
+
+inline int grid_for(int64_t items, int per_block, int cap = 1 << 30) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ---- launch wrappers (defined in fastsv.hip) ----
+enum DenseMode : int { kDenseIota = 0, kDenseGather = 1, kDenseBaseIota = 2, kDenseBaseGather = 3 };
+
+// F = Fn = G = M = base + i for i in [0, n)
+void launch_init(hipStream_t s, int n, int *F, int *Fn, int *G, int *M, int base = 0);
+// tiles of one CSR graph whose entries are [e_begin, e_end) of col and whose
+// rows are [r_begin, r_begin + nrows) with absolute row_ptr values
+void launch_build_tiles(hipStream_t s, int nrows, int r_begin, int e_begin, int e_end, const int *rp, Tile *tiles);
+void launch_dense(hipStream_t s, int mode, const Tile *tiles, int ntiles, const int *rp, const int *col,
+                  const int *vbase, const int *F, int *Fn, const int *G, int *M);
+void launch_sparse(hipStream_t s, const int *frontier, const int *eoff, int fcnt, int edges, const int *rp,
+                   const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M);
+void launch_zero_iter(hipStream_t s, IterCounters *ic);
+void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
+                        int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter);
+
+}  // namespace fsv

@@ -1,0 +1,937 @@
+// Device kernels of the FastSV library (gfx950).  Included by fastsv.hip only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "engine.h"
+
+namespace fsv {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Inclusive min-scan over the lanes of a wave, restricted to runs of equal
+// keys; keys must be nondecreasing across lanes.
+__device__ __forceinline__ int seg_min_scan(int key, int val) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int ov = __shfl_up(val, d, kWave);
+        int ok = __shfl_up(key, d, kWave);
+        if (lane >= d && ok == key) val = min(val, ov);
+    }
+    return val;
+}
+
+__device__ __forceinline__ int wave_incl_sum(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int o = __shfl_up(v, d, kWave);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Apply the result m of row u: M update, then the two hooks if they can
+// change anything.  `shared_row` is set when other tiles also hold entries of
+// row u (its M slot then needs an atomic).
+// kIota (first iteration): F = G = M = iota, so m < u is the whole filter, and
+// both hooks target u itself; a row owned by one tile is then the only writer
+// of M[u] and Fn[u] and stores them directly.
+template <bool kIota>
+__device__ __forceinline__ void finish_row(int u, int m, bool shared_row, const int *__restrict__ F,
+                                           int *__restrict__ Fn, const int *__restrict__ G,
+                                           int *__restrict__ M) {
+    if (kIota) {
+        if (m < u) {
+            if (shared_row) {
+                atomicMin(M + u, m);
+                atomicMin(Fn + u, m);
+            } else {
+                M[u] = m;
+                Fn[u] = m;
+            }
+        }
+        return;
+    }
+    int mu = M[u];
+    if (m < mu) {
+        if (shared_row) atomicMin(M + u, m);
+        else M[u] = m;
+    }
+    int gu = G[u];
+    if (m < gu) {
+        atomicMin(Fn + u, m);
+        int x = F[u];
+        if (x != u) atomicMin(Fn + x, m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile table of one CSR graph whose rows are [r_begin, r_begin + nrows) (with
+// absolute row_ptr values) and whose entries are [e_begin, e_end): tile t
+// covers entries [e_begin + t*T, min(e_begin + (t+1)*T, e_end)).  The row
+// holding a tile's first entry writes r_lo, the row holding its last entry
+// writes r_hi; every tile gets exactly one writer of each.
+// ---------------------------------------------------------------------------
+__global__ void k_build_tiles(int nrows, int r_begin, int e_begin, int e_end, const int *__restrict__ rp,
+                              Tile *__restrict__ tiles) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    const int r = r_begin + i;
+    const int s = rp[r] - e_begin, e = rp[r + 1] - e_begin;
+    if (s >= e) return;
+    const int len = e_end - e_begin;
+    for (int t = s / kTileEntries; t <= (e - 1) / kTileEntries; ++t) {
+        int t0 = t * kTileEntries;
+        int last = min(t0 + kTileEntries, len) - 1;
+        if (t0 >= s && t0 < e) {
+            tiles[t].e0 = e_begin + t0;
+            tiles[t].e1 = e_begin + last + 1;
+            tiles[t].r_lo = r;
+        }
+        if (last >= s && last < e) tiles[t].r_hi = r;
+    }
+}
+
+// Optional argument check on the device: row_ptr monotone with the stated
+// ends, every column id in [0,n).
+__global__ void k_validate(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ col,
+                           Counters *ctr) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int r = i; r < n; r += stride) bad |= rp[r] > rp[r + 1];
+    if (i == 0) bad |= (rp[0] != 0) || (rp[n] != nnz);
+    for (int e = i; e < nnz; e += stride) {
+        int c = col[e];
+        bad |= (c < 0) || (c >= n);
+    }
+    if (bad) atomicOr(&ctr->status, 1);
+}
+
+// F = Fn = G = M = iota over global ids base + i.
+__global__ void k_init(int n, int *__restrict__ F, int *__restrict__ Fn, int *__restrict__ G,
+                       int *__restrict__ M, int base) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) {
+        int v = base + u;
+        F[u] = v;
+        Fn[u] = v;
+        G[u] = v;
+        M[u] = v;
+    }
+}
+
+__global__ void k_zero_counters(Counters *ctr) {
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 2; ++i) ctr->it[i].packed = 0ull;
+        ctr->status = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile reduction: the pull SpMV over (select2nd, min), row by row.
+// One wave per tile of 1024 consecutive entries of a CSR; lane l owns entries
+// [e0 + 16 l, e0 + 16 l + 16).  Rows of the tile are located through a copy of
+// row_ptr[r_lo .. r_hi+1] in LDS (global memory when the window is larger).
+// Each lane reduces its rows sequentially; rows crossing lanes are combined
+// with a segmented min-scan; rows crossing tiles are flagged `shared`.
+//
+// Modes
+//   kIota       first iteration: G is the identity, so the gathered value is
+//               the column id itself
+//   kGather     m = min G[col]; finish = M update + hooks
+//   kBaseIota / kBaseGather
+//               the same for a batch of graphs with local column ids: the
+//               global id is col + base[row]
+//   kPhase      column-blocked pass: the CSR's rows are segments (row, column
+//               block); finish = M update of the segment's row only (the
+//               hooks run afterwards from M, see k_hook_rows)
+// ---------------------------------------------------------------------------
+enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kPhase = 4 };
+
+template <int kMode>
+__device__ __forceinline__ void finish_tile_row(int r, int m, bool shared_row, const int *__restrict__ aux,
+                                                const int *__restrict__ F, int *__restrict__ Fn,
+                                                const int *__restrict__ G, int *__restrict__ M) {
+    if (kMode == kPhase) {
+        int sr = aux[r];
+        int u = sr & 0x7fffffff;
+        bool sh = shared_row || sr < 0;
+        if (m < M[u]) {
+            if (sh) atomicMin(M + u, m);
+            else M[u] = m;
+        }
+    } else {
+        finish_row<kMode == kIota || kMode == kBaseIota>(r, m, shared_row, F, Fn, G, M);
+    }
+}
+
+template <int kMode>
+__global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
+    const Tile *__restrict__ tiles, int ntiles, const int *__restrict__ rp, const int *__restrict__ col,
+    const int *__restrict__ aux, const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G,
+    int *__restrict__ M) {
+    constexpr bool kBase = kMode == kBaseIota || kMode == kBaseGather;
+    constexpr bool kNoGather = kMode == kIota || kMode == kBaseIota;
+    __shared__ int win[kHookWaves][kRowWin];   // row_ptr[r_lo .. r_hi+1]
+    __shared__ int rmin[kHookWaves][kRowWin];  // per-row minimum of this tile
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int t = blockIdx.x * kHookWaves + wave;
+    const bool tile_ok = t < ntiles;
+    Tile T = tile_ok ? tiles[t] : Tile{0, 0, 0, -1};
+    const int a = T.e0 + lane * kPerLane;
+    const int cnt = tile_ok ? max(0, min(kPerLane, T.e1 - a)) : 0;
+
+    // column ids first (streamed, kept out of the caches' way), then the gathers,
+    // so both are in flight while the row window is staged
+    int c[kPerLane];
+    if (cnt == kPerLane && ((reinterpret_cast<uintptr_t>(col + a) & 15) == 0)) {
+        const v4i *p = reinterpret_cast<const v4i *>(col + a);
+#pragma unroll
+        for (int q = 0; q < kPerLane / 4; ++q) {
+            v4i v = __builtin_nontemporal_load(p + q);
+            c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) c[j] = j < cnt ? __builtin_nontemporal_load(col + a + j) : 0;
+    }
+    int g[kPerLane];
+    if (!kBase) {
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) g[j] = j < cnt ? (kNoGather ? c[j] : G[c[j]]) : INT_MAX;
+    }
+
+    const int nwin = T.r_hi - T.r_lo + 2;
+    const bool in_lds = tile_ok && nwin <= kRowWin;
+    if (in_lds)
+        for (int i = lane; i < nwin; i += kWave) {
+            win[wave][i] = rp[T.r_lo + i];
+            rmin[wave][i] = INT_MAX;
+        }
+    __syncthreads();
+    const int *wrow = &win[wave][0];
+    auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
+
+    int row0 = 0, nxt = 0;
+    if (cnt > 0) {
+        // row containing entry a: the last row r in [r_lo, r_hi] with row_ptr[r] <= a
+        int lo = T.r_lo, hi = T.r_hi;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (rpw(mid) <= a) lo = mid;
+            else hi = mid - 1;
+        }
+        row0 = lo;
+        nxt = rpw(row0 + 1);
+    }
+    if (kBase) {
+        // batched graphs: local column ids, shifted by the base of the row's graph
+        int r = row0, nx = nxt, b = cnt > 0 ? aux[row0] : 0;
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            if (j < cnt) {
+                int e = a + j;
+                if (e >= nx) {
+                    do { ++r; nx = rpw(r + 1); } while (e >= nx);
+                    b = aux[r];
+                }
+                g[j] = kNoGather ? c[j] + b : G[c[j] + b];
+            } else {
+                g[j] = INT_MAX;
+            }
+        }
+    }
+
+    if (in_lds) {
+        // every row segment of the lane folds its minimum into the tile's LDS
+        // row array; rows are then finished together with coalesced accesses
+        int row = row0, cur = INT_MAX;
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            if (j < cnt) {
+                int e = a + j;
+                if (e >= nxt) {
+                    atomicMin(&rmin[wave][row - T.r_lo], cur);
+                    do { ++row; nxt = rpw(row + 1); } while (e >= nxt);
+                    cur = INT_MAX;
+                }
+                cur = min(cur, g[j]);
+            }
+        }
+        if (cnt > 0) atomicMin(&rmin[wave][row - T.r_lo], cur);
+    }
+    __syncthreads();
+    if (!tile_ok) return;
+    if (in_lds) {
+        const int nrows = nwin - 1;
+        for (int i = lane; i < nrows; i += kWave) {
+            int m = rmin[wave][i];
+            if (m == INT_MAX) continue;  // empty row
+            bool shared_row = (i == 0 && wrow[0] < T.e0) || (i == nrows - 1 && wrow[nrows] > T.e1);
+            finish_tile_row<kMode>(T.r_lo + i, m, shared_row, aux, F, Fn, G, M);
+        }
+        return;
+    }
+
+    // wide window (rows far apart): per-lane finish, rows crossing lanes are
+    // combined with a segmented min-scan
+    int row = row0, cur = INT_MAX, first_min = INT_MAX;
+    bool first_closed = false;
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+        if (j < cnt) {
+            int e = a + j;
+            if (e >= nxt) {
+                if (!first_closed) {
+                    first_min = cur;
+                    first_closed = true;
+                } else {
+                    finish_tile_row<kMode>(row, cur, false, aux, F, Fn, G, M);  // row inside this lane
+                }
+                do { ++row; nxt = rpw(row + 1); } while (e >= nxt);
+                cur = INT_MAX;
+            }
+            cur = min(cur, g[j]);
+        }
+    }
+    const bool first_is_head = cnt > 0 && rpw(row0) == a;
+    const int key = cnt > 0 ? row : INT_MAX;
+    const int S = seg_min_scan(key, cnt > 0 ? cur : INT_MAX);
+    const int prevS = __shfl_up(S, 1, kWave);
+    const int next_head = __shfl_down(first_is_head ? 1 : 0, 1, kWave);
+    const int next_cnt = __shfl_down(cnt, 1, kWave);
+    if (cnt == 0) return;
+    if (first_closed) {
+        int m = first_min;
+        if (lane > 0 && !first_is_head) m = min(m, prevS);
+        finish_tile_row<kMode>(row0, m, rpw(row0) < T.e0, aux, F, Fn, G, M);
+    }
+    const bool ends_here = lane == kWave - 1 || next_cnt == 0 || next_head;
+    if (ends_here) {
+        bool shared_row = rpw(row) < T.e0 || rpw(row + 1) > T.e1;
+        finish_tile_row<kMode>(row, S, shared_row, aux, F, Fn, G, M);
+    }
+}
+
+// Hooks from the accumulated M after the column-blocked passes:
+//   if M[u] < G[u]:  Fn[u] <-min M[u],  Fn[F[u]] <-min M[u].
+// M[u] = min(M_{k-1}[u], m[u]); the older part never beats G[u] (it is at
+// least f_{k-1}[u] >= G[u]), so this is the same filter and value as hooking
+// with the fresh m[u].
+__global__ void k_hook_rows(int n, const int *__restrict__ M, const int *__restrict__ G,
+                            const int *__restrict__ F, int *__restrict__ Fn) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) {
+        int m = M[u];
+        if (m < G[u]) {
+            atomicMin(Fn + u, m);
+            int x = F[u];
+            if (x != u) atomicMin(Fn + x, m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column-blocked layout (built once per solve for large graphs with sorted
+// rows).  Column block b holds the vertices [b W, (b+1) W).  The entries are
+// regrouped, stably, by block: block-major, then source tile, then row.  A
+// segment is the run of one row's entries inside one source tile and one
+// block; block b's segments form a CSR over its region of cb_col.  A dense
+// iteration then runs one pass per block, whose gathers stay inside a
+// W-vertex slice of G that fits in L2, and combines the per-segment minima in
+// M.  A segment whose row also has entries in another source tile is flagged
+// (sign bit of seg_row): its M update is atomic.
+// ---------------------------------------------------------------------------
+// Row walk shared by the two preparation passes: for lane entries
+// [a, a+cnt), the row of each entry, its block, and whether it starts a segment.
+struct PrepLane {
+    int row[kPerLane];
+    int blk[kPerLane];
+    bool head[kPerLane];
+};
+
+__device__ __forceinline__ void prep_lane(const Tile &T, const int *__restrict__ rp, const int *__restrict__ col,
+                                          const int *wrow, bool in_lds, int a, int cnt, int wshift, PrepLane &P,
+                                          int &unsorted) {
+    auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
+    const int lane = lane_id();
+    int c[kPerLane];
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) c[j] = j < cnt ? col[a + j] : 0;
+    // column id of the entry before a (previous lane's last entry)
+    int prev_c = __shfl_up(c[kPerLane - 1], 1, kWave);
+    int row = 0, nxt = 0;
+    if (cnt > 0) {
+        int lo = T.r_lo, hi = T.r_hi;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (rpw(mid) <= a) lo = mid;
+            else hi = mid - 1;
+        }
+        row = lo;
+        nxt = rpw(row + 1);
+    }
+    int pc = prev_c;
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+        P.head[j] = false;
+        P.blk[j] = 0;
+        P.row[j] = row;
+        if (j < cnt) {
+            int e = a + j;
+            while (e >= nxt) { ++row; nxt = rpw(row + 1); }
+            int b = c[j] >> wshift;
+            b = b < 0 ? 0 : (b >= kMaxBlocks ? kMaxBlocks - 1 : b);  // only out-of-range ids get clamped
+            bool row_start = e == rpw(row);
+            bool tile_start = (lane == 0 && j == 0);
+            P.head[j] = tile_start || row_start || (pc >> wshift) != b;
+            if (!tile_start && !row_start && pc > c[j]) unsorted = 1;
+            P.row[j] = row;
+            P.blk[j] = b;
+            pc = c[j];
+        }
+    }
+}
+
+// Pass 1: per (block, source tile) counts of entries and segments, block-major.
+__global__ __launch_bounds__(kWave) void k_cb_count(const Tile *__restrict__ tiles, int ntiles,
+                                                    const int *__restrict__ rp, const int *__restrict__ col,
+                                                    int wshift, int nblk, int *__restrict__ cnt_e,
+                                                    int *__restrict__ cnt_s, int *__restrict__ flags) {
+    __shared__ int win[kRowWin];
+    __shared__ int h_e[kMaxBlocks], h_s[kMaxBlocks];
+    const int t = blockIdx.x;
+    const int lane = lane_id();
+    const Tile T = tiles[t];
+    const int nwin = T.r_hi - T.r_lo + 2;
+    const bool in_lds = nwin <= kRowWin;
+    if (in_lds)
+        for (int i = lane; i < nwin; i += kWave) win[i] = rp[T.r_lo + i];
+    for (int b = lane; b < nblk; b += kWave) { h_e[b] = 0; h_s[b] = 0; }
+    __syncthreads();
+    const int a = T.e0 + lane * kPerLane;
+    const int cnt = max(0, min(kPerLane, T.e1 - a));
+    PrepLane P;
+    int unsorted = 0;
+    prep_lane(T, rp, col, win, in_lds, a, cnt, wshift, P, unsorted);
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+        if (j < cnt) {
+            atomicAdd(&h_e[P.blk[j]], 1);
+            if (P.head[j]) atomicAdd(&h_s[P.blk[j]], 1);
+        }
+    }
+    if (unsorted) atomicOr(flags, 1);
+    __syncthreads();
+    for (int b = lane; b < nblk; b += kWave) {
+        cnt_e[(int64_t)b * ntiles + t] = h_e[b];
+        cnt_s[(int64_t)b * ntiles + t] = h_s[b];
+    }
+}
+
+// Exclusive scan of int32 (totals below 2^31): block-local scans of 4096
+// items, a single-block scan of the block sums, then the add-back.
+__device__ int block_excl_scan(int v, int *s_tmp, int &total) {
+    // s_tmp: kScanThreads / kWave ints
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    int incl = wave_incl_sum(v);
+    if (lane == kWave - 1) s_tmp[wave] = incl;
+    __syncthreads();
+    int wpre = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+        int x = s_tmp[w];
+        if (w < wave) wpre += x;
+        tot += x;
+    }
+    __syncthreads();
+    total = tot;
+    return wpre + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int *__restrict__ x, int64_t len,
+                                                              int *__restrict__ sums) {
+    __shared__ int s_tmp[kScanThreads / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    int v = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t k = base + (int64_t)i * kScanThreads + threadIdx.x;
+        if (k < len) v += x[k];
+    }
+    int total;
+    block_excl_scan(v, s_tmp, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of sums[0..m) in place, total in sums[m]
+__global__ __launch_bounds__(1024) void k_scan_top(int *__restrict__ sums, int m) {
+    __shared__ int s_tmp[1024 / kWave];
+    __shared__ int s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int base = 0; base < m; base += 1024) {
+        int k = base + threadIdx.x;
+        int v = k < m ? sums[k] : 0;
+        int total;
+        int ex = block_excl_scan(v, s_tmp, total);
+        int carry = s_carry;
+        if (k < m) sums[k] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[m] = s_carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int *__restrict__ x, int64_t len,
+                                                            const int *__restrict__ sums, int *__restrict__ y) {
+    __shared__ int s_tmp[kScanThreads / kWave];
+    // each thread owns kScanItems consecutive items of the block
+    int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t k = base + i;
+        v[i] = k < len ? x[k] : 0;
+        sum += v[i];
+    }
+    int total;
+    int ex = block_excl_scan(sum, s_tmp, total);
+    int run = sums[blockIdx.x] + ex;
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t k = base + i;
+        if (k < len) y[k] = run;
+        run += v[i];
+    }
+}
+
+// Block bases: entries of block b start at cbb[b] (4-entry aligned), its
+// segments at sbb[b]; tb[b] = first phase tile of block b.  Also writes the
+// per-block sentinel of the segment pointer array.  Single thread.
+__global__ void k_cb_bases(const int *__restrict__ off_e, const int *__restrict__ off_s, int ntiles, int nblk,
+                           int nnz, const int *__restrict__ total_s, CbInfo *__restrict__ info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int base = 0, tiles = 0;
+    for (int b = 0; b < nblk; ++b) {
+        int start = off_e[(int64_t)b * ntiles];
+        int end = b + 1 < nblk ? off_e[(int64_t)(b + 1) * ntiles] : nnz;
+        int len = end - start;
+        info->cbb[b] = base;
+        info->len[b] = len;
+        info->sbb[b] = off_s[(int64_t)b * ntiles];
+        info->tb[b] = tiles;
+        tiles += (len + kTileEntries - 1) / kTileEntries;
+        base += (len + 3) & ~3;
+    }
+    info->cbb[nblk] = base;
+    info->sbb[nblk] = *total_s;
+    info->tb[nblk] = tiles;
+}
+
+// Pass 2: stable scatter of entries into cb_col and of segment heads into
+// seg_ptr / seg_row.
+__global__ __launch_bounds__(kWave) void k_cb_scatter(const Tile *__restrict__ tiles, int ntiles,
+                                                      const int *__restrict__ rp, const int *__restrict__ col,
+                                                      int wshift, int nblk, const int *__restrict__ off_e,
+                                                      const int *__restrict__ off_s, const CbInfo *__restrict__ info,
+                                                      int *__restrict__ cb_col, int *__restrict__ seg_ptr,
+                                                      int *__restrict__ seg_row) {
+    __shared__ int win[kRowWin];
+    __shared__ unsigned short pe[kWave][kMaxBlocks];  // per-lane entry counts -> exclusive prefix over lanes
+    __shared__ unsigned short ps[kWave][kMaxBlocks];  // per-lane head counts  -> exclusive prefix over lanes
+    const int t = blockIdx.x;
+    const int lane = lane_id();
+    const Tile T = tiles[t];
+    const int nwin = T.r_hi - T.r_lo + 2;
+    const bool in_lds = nwin <= kRowWin;
+    if (in_lds)
+        for (int i = lane; i < nwin; i += kWave) win[i] = rp[T.r_lo + i];
+    for (int b = 0; b < nblk; ++b) { pe[lane][b] = 0; ps[lane][b] = 0; }
+    __syncthreads();
+    const int a = T.e0 + lane * kPerLane;
+    const int cnt = max(0, min(kPerLane, T.e1 - a));
+    PrepLane P;
+    int unsorted = 0;
+    prep_lane(T, rp, col, win, in_lds, a, cnt, wshift, P, unsorted);
+    int lre[kPerLane], lrs[kPerLane];
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+        if (j < cnt) {
+            lre[j] = pe[lane][P.blk[j]]++;
+            lrs[j] = P.head[j] ? ps[lane][P.blk[j]]++ : 0;
+        }
+    }
+    __syncthreads();
+    // exclusive prefix over lanes, one block column per lane
+    for (int b = lane; b < nblk; b += kWave) {
+        int re = 0, rs = 0;
+        for (int l = 0; l < kWave; ++l) {
+            int xe = pe[l][b], xs = ps[l][b];
+            pe[l][b] = (unsigned short)re;
+            ps[l][b] = (unsigned short)rs;
+            re += xe;
+            rs += xs;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) {
+        if (j < cnt) {
+            const int b = P.blk[j];
+            const int64_t k = (int64_t)b * ntiles + t;
+            const int pos = off_e[k] - off_e[(int64_t)b * ntiles] + info->cbb[b] + pe[lane][b] + lre[j];
+            cb_col[pos] = col[a + j];
+            if (P.head[j]) {
+                const int sp = off_s[k] + ps[lane][b] + lrs[j];
+                const int u = P.row[j];
+                const bool shared = rp[u] < T.e0 || rp[u + 1] > T.e1;
+                seg_ptr[sp + b] = pos;
+                seg_row[sp] = shared ? (u | (int)0x80000000) : u;
+            }
+        }
+    }
+}
+
+__global__ void k_cb_sentinels(int nblk, const CbInfo *__restrict__ info, int *__restrict__ seg_ptr) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nblk) seg_ptr[info->sbb[b + 1] + b] = info->cbb[b] + info->len[b];
+}
+
+// Phase tile table: for segment s of block b (local index r), the tiles of
+// block b whose first / last entry lies in the segment.
+__global__ void k_cb_tiles(int nblk, const CbInfo *__restrict__ info, const int *__restrict__ seg_ptr,
+                           Tile *__restrict__ tiles) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= info->sbb[nblk]) return;
+    int lo = 0, hi = nblk - 1;  // block of s: last b with sbb[b] <= s
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (info->sbb[mid] <= s) lo = mid;
+        else hi = mid - 1;
+    }
+    const int b = lo;
+    const int r = s - info->sbb[b];
+    const int *rpb = seg_ptr + info->sbb[b] + b;
+    const int base = info->cbb[b], end = base + info->len[b];
+    const int st = rpb[r], en = rpb[r + 1];
+    Tile *tb = tiles + info->tb[b];
+    for (int t = (st - base) / kTileEntries; t <= (en - 1 - base) / kTileEntries; ++t) {
+        int t0 = base + t * kTileEntries;
+        int last = min(t0 + kTileEntries, end) - 1;
+        if (t0 >= st && t0 < en) {
+            tb[t].e0 = t0;
+            tb[t].e1 = last + 1;
+            tb[t].r_lo = r;
+        }
+        if (last >= st && last < en) tb[t].r_hi = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grandparent pass + termination test + frontier compaction.
+//   G_k[u] = Fn[Fn[u]];  changed = G_k[u] != G_{k-1}[u];  NextFn[u] = G_k[u]
+// The changed vertices are counted (termination test) and, when requested,
+// appended to the frontier list together with the exclusive prefix of their
+// degrees (the sparse push balances edge slots with it).  Count and degree sum
+// share one 64-bit counter (count in the high half), updated once per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kGpThreads) void k_grandparent(
+    int n, const int *__restrict__ Fn, int *__restrict__ G, int *__restrict__ next_fn,
+    const int *__restrict__ rp, int *__restrict__ frontier, int *__restrict__ eoff,
+    IterCounters *__restrict__ ctr, int write_frontier, int *__restrict__ lastk, int iter) {
+    constexpr int kW = kGpThreads / kWave;
+    __shared__ int s_cnt[kGpPerThread][kW];
+    __shared__ int s_deg[kGpPerThread][kW];
+    __shared__ unsigned long long s_base;
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int base_u = blockIdx.x * kGpBlockVerts;
+    bool ch[kGpPerThread];
+    int deg[kGpPerThread];
+#pragma unroll
+    for (int i = 0; i < kGpPerThread; ++i) {
+        int u = base_u + i * kGpThreads + threadIdx.x;
+        ch[i] = false;
+        deg[i] = 0;
+        if (u < n) {
+            int p = Fn[u];
+            int g = Fn[p];
+            int old = G[u];
+            next_fn[u] = g;
+            if (g != old) {
+                G[u] = g;
+                ch[i] = true;
+                if (lastk) lastk[u] = iter;
+                if (write_frontier) deg[i] = rp[u + 1] - rp[u];
+            }
+        }
+    }
+    int rank[kGpPerThread], dpre[kGpPerThread];
+#pragma unroll
+    for (int i = 0; i < kGpPerThread; ++i) {
+        unsigned long long bal = __ballot(ch[i]);
+        rank[i] = __popcll(bal & ((1ull << lane) - 1ull));
+        int incl = wave_incl_sum(deg[i]);
+        dpre[i] = incl - deg[i];
+        if (lane == kWave - 1) {
+            s_cnt[i][wave] = __popcll(bal);
+            s_deg[i][wave] = incl;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long c = 0, d = 0;
+        for (int i = 0; i < kGpPerThread; ++i)
+            for (int w = 0; w < kW; ++w) {
+                int cc = s_cnt[i][w], dd = s_deg[i][w];
+                s_cnt[i][w] = (int)c;
+                s_deg[i][w] = (int)d;
+                c += cc;
+                d += dd;
+            }
+        s_base = c ? atomicAdd(&ctr->packed, (c << 32) | d) : 0ull;
+    }
+    __syncthreads();
+    if (!write_frontier) return;
+    const unsigned long long b = s_base;
+    const int bc = (int)(b >> 32), bd = (int)(b & 0xffffffffull);
+#pragma unroll
+    for (int i = 0; i < kGpPerThread; ++i) {
+        if (ch[i]) {
+            int u = base_u + i * kGpThreads + threadIdx.x;
+            int pos = bc + s_cnt[i][wave] + rank[i];
+            frontier[pos] = u;
+            eoff[pos] = bd + s_deg[i][wave] + dpre[i];
+        }
+    }
+}
+
+__global__ void k_zero_iter_counters(IterCounters *c) {
+    if (threadIdx.x == 0) c->packed = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Sparse push: for every frontier vertex v and neighbour u,
+//   old = atomicMin(M[u], G[v]);  if G[v] < old and G[v] < G[u]: hooks on u.
+// Edge slots are spread evenly over workgroups: workgroup b owns slots
+// [b*S, (b+1)*S) of the concatenated frontier rows; the frontier range it
+// touches is found with a 64-way search over the edge offsets.
+// ---------------------------------------------------------------------------
+__device__ int wave_upper_search(const int *__restrict__ eoff, int cnt, int s) {
+    // largest i in [0, cnt) with eoff[i] <= s (eoff[0] = 0 <= s)
+    const int lane = lane_id();
+    int lo = 0, hi = cnt;  // answer in [lo, hi)
+    while (hi - lo > kWave) {
+        int step = (hi - lo + kWave - 1) / kWave;
+        int p = lo + lane * step;
+        bool ok = p < hi && eoff[p] <= s;
+        unsigned long long bal = __ballot(ok);
+        int last = kWave - 1 - __clzll(bal);  // bal != 0: lane 0 probes lo, eoff[lo] <= s
+        lo = lo + last * step;
+        hi = min(lo + step, hi);
+    }
+    int p = lo + lane;
+    bool ok = p < hi && eoff[p] <= s;
+    unsigned long long bal = __ballot(ok);
+    return lo + (kWave - 1 - __clzll(bal));
+}
+
+template <bool kHasBase>
+__global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
+    const int *__restrict__ frontier, const int *__restrict__ eoff, int fcnt, int total,
+    const int *__restrict__ rp, const int *__restrict__ col, const int *__restrict__ vbase,
+    const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G, int *__restrict__ M) {
+    __shared__ int s_range[2];
+    __shared__ int s_off[kPushSlots + 1];
+    __shared__ int s_row[kPushSlots + 1];
+    __shared__ int s_val[kPushSlots + 1];
+    __shared__ int s_base[kHasBase ? kPushSlots + 1 : 1];
+    const int s0 = blockIdx.x * kPushSlots;
+    const int s1 = min(s0 + kPushSlots, total);
+    if (threadIdx.x < kWave) {
+        int i0 = wave_upper_search(eoff, fcnt, s0);
+        int i1 = wave_upper_search(eoff, fcnt, s1 - 1);
+        if (threadIdx.x == 0) { s_range[0] = i0; s_range[1] = i1; }
+    }
+    __syncthreads();
+    const int i0 = s_range[0], i1 = s_range[1];
+    // every frontier vertex with edges owns >= 1 slot, so a block's slots touch at
+    // most kPushSlots of them; vertices without edges (possible only when the
+    // matrix is not symmetric) can make the range longer, then the block
+    // searches the offsets in global memory instead
+    const int nv = i1 - i0 + 1;
+    const bool in_lds = nv <= kPushSlots + 1;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < nv; i += kPushThreads) {
+            int v = frontier[i0 + i];
+            s_off[i] = eoff[i0 + i];
+            s_row[i] = rp[v];
+            s_val[i] = G[v];
+            if (kHasBase) s_base[i] = vbase[v];
+        }
+    }
+    __syncthreads();
+    for (int s = s0 + threadIdx.x; s < s1; s += kPushThreads) {
+        // frontier entry owning slot s: the last i with eoff[i] <= s
+        int lo = 0, hi = nv - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            int om = in_lds ? s_off[mid] : eoff[i0 + mid];
+            if (om <= s) lo = mid;
+            else hi = mid - 1;
+        }
+        int off, row, val, vb = 0;
+        if (in_lds) {
+            off = s_off[lo]; row = s_row[lo]; val = s_val[lo];
+            if (kHasBase) vb = s_base[lo];
+        } else {
+            int v = frontier[i0 + lo];
+            off = eoff[i0 + lo]; row = rp[v]; val = G[v];
+            if (kHasBase) vb = vbase[v];
+        }
+        int u = col[row + (s - off)] + vb;
+        int old = atomicMin(M + u, val);
+        if (val < old) {
+            int gu = G[u];
+            if (val < gu) {
+                atomicMin(Fn + u, val);
+                int x = F[u];
+                if (x != u) atomicMin(Fn + x, val);
+            }
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Edge-list entry: symmetric CSR built on the device.  Edge (u,v) is stored as
+// v in row u and u in row v (a self loop twice in its row), like the
+// reference graphs.  Order inside a row follows the atomic cursor; the method
+// does not depend on it.
+// ---------------------------------------------------------------------------
+__global__ void k_validate_edges(int64_t m, int n, const int *__restrict__ src, const int *__restrict__ dst,
+                                 Counters *ctr) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t e = i; e < m; e += stride) {
+        int a = src[e], b = dst[e];
+        bad |= a < 0 || a >= n || b < 0 || b >= n;
+    }
+    if (bad) atomicOr(&ctr->status, 1);
+}
+
+__global__ void k_fill(int n, int *__restrict__ x, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) x[u] = v;
+}
+
+__global__ void k_edge_degrees(int64_t m, const int *__restrict__ src, const int *__restrict__ dst,
+                               int *__restrict__ deg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = i; e < m; e += stride) {
+        atomicAdd(deg + src[e], 1);
+        atomicAdd(deg + dst[e], 1);
+    }
+}
+
+// rp[0..n) holds the exclusive prefix of the degrees; set rp[n] and a copy of
+// the row starts as write cursors.
+__global__ void k_edge_rowptr_tail(int n, int *__restrict__ rp, const int *__restrict__ total,
+                                   int *__restrict__ cursor) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) cursor[u] = rp[u];
+    if (i == 0) rp[n] = *total;
+}
+
+__global__ void k_edge_scatter(int64_t m, const int *__restrict__ src, const int *__restrict__ dst,
+                               int *__restrict__ cursor, int *__restrict__ col) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = i; e < m; e += stride) {
+        int a = src[e], b = dst[e];
+        col[atomicAdd(cursor + a, 1)] = b;
+        col[atomicAdd(cursor + b, 1)] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batch of graphs solved as one block-diagonal graph.  Graph g owns the global
+// vertices [vtx_off[g], vtx_off[g+1]) and entries [edge_off[g], edge_off[g+1]);
+// its column ids are local.  Values of f and gf are global ids, so graphs
+// never exchange anything and each follows its own trajectory exactly.
+// One workgroup per graph for the per-graph passes below.
+// ---------------------------------------------------------------------------
+__global__ void k_batch_validate(int ngraphs, int total_n, int total_nnz, const int *__restrict__ vtx_off,
+                                 const int *__restrict__ edge_off, const int *__restrict__ rp,
+                                 const int *__restrict__ col, Counters *ctr) {
+    const int g = blockIdx.x;
+    if (g >= ngraphs) return;
+    const int v0 = vtx_off[g], v1 = vtx_off[g + 1], e0 = edge_off[g], e1 = edge_off[g + 1];
+    bool bad = v0 < 0 || v1 < v0 || v1 > total_n || e0 < 0 || e1 < e0 || e1 > total_nnz;
+    if (g == 0) bad |= v0 != 0 || e0 != 0;
+    if (g == ngraphs - 1) bad |= v1 != total_n || e1 != total_nnz;
+    if (!bad) {
+        bad |= rp[v0] != e0 || rp[v1] != e1;
+        const int nloc = v1 - v0;
+        for (int r = v0 + (int)threadIdx.x; r < v1 && !bad; r += blockDim.x) bad |= rp[r] > rp[r + 1];
+        if (!bad)
+            for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
+                int c = col[e];
+                bad |= c < 0 || c >= nloc;
+            }
+    }
+    if (bad) atomicOr(&ctr->status, 1);
+}
+
+__global__ void k_batch_bases(int ngraphs, const int *__restrict__ vtx_off, int *__restrict__ vbase,
+                              int *__restrict__ lastk) {
+    const int g = blockIdx.x;
+    if (g >= ngraphs) return;
+    const int v0 = vtx_off[g], v1 = vtx_off[g + 1];
+    for (int u = v0 + (int)threadIdx.x; u < v1; u += blockDim.x) {
+        vbase[u] = v0;
+        lastk[u] = 0;
+    }
+}
+
+// labels in local ids and per-graph iteration counts: 1 + the last iteration
+// in which a grandparent of the graph changed (-1 if that is the final
+// iteration of a capped run, i.e. the graph had not converged; 0 for a graph
+// without vertices).
+__global__ void k_batch_finish(int ngraphs, const int *__restrict__ vtx_off, const int *__restrict__ src,
+                               const int *__restrict__ lastk, int *__restrict__ labels, int *__restrict__ iters,
+                               int final_iter, int capped) {
+    __shared__ int s_max[16];
+    const int g = blockIdx.x;
+    if (g >= ngraphs) return;
+    const int v0 = vtx_off[g], v1 = vtx_off[g + 1];
+    int mx = 0;
+    for (int u = v0 + (int)threadIdx.x; u < v1; u += blockDim.x) {
+        labels[u] = src[u] - v0;
+        mx = max(mx, lastk[u]);
+    }
+    for (int d = kWave / 2; d > 0; d >>= 1) mx = max(mx, __shfl_down(mx, d, kWave));
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) s_max[wave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = max(m, s_max[w]);
+        // an empty graph needs no iteration (the solo call returns at once)
+        iters[g] = v1 == v0 ? 0 : ((capped && m == final_iter) ? -1 : m + 1);
+    }
+}
+
+}  // namespace fsv
