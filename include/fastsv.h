@@ -190,6 +190,64 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
                         const int32_t *d_col_idx, int32_t *d_labels, int32_t *d_iters, void *d_ws,
                         size_t ws_bytes, hipStream_t stream, const fastsv_opts *opts, fastsv_stats *stats);
 
+/*
+ * Serving: continuous batching of connected-components requests.
+ *
+ * The server owns a device pool of max_vertices vertices and max_entries
+ * stored entries.  A request (host CSR, copied at submit) is admitted first
+ * come first served as soon as a slot, n+1 pool vertices and nnz pool
+ * entries are free.  Each fastsv_server_step runs one iteration of the method
+ * (Algorithm 3, dense or sparse-frontier SpMV as for fastsv_cc_csr) for ALL
+ * resident graphs at once; graphs admitted at a step start their first
+ * iteration in it, and a graph retires after the first step in which none of
+ * its grandparents changed (termination test of Sec. 3.4 for that graph).
+ * Graphs never exchange values, so every request gets exactly the labels and
+ * the iteration count it would get alone.  On retirement the local labels
+ * are copied into h_labels_out and the iteration count into *h_iters_out, and
+ * the ticket becomes available from fastsv_server_poll.
+ *
+ * Threading: a server is driven from one host thread; it uses `stream` for
+ * all device work and synchronises it inside fastsv_server_step.
+ */
+typedef struct fastsv_server fastsv_server;
+
+typedef struct {
+    int64_t submitted, admitted, completed, steps, dense_steps, sparse_steps;
+} fastsv_server_stats;
+
+/* Device bytes the pool of a server with these limits occupies. */
+size_t fastsv_server_pool_bytes(int32_t max_vertices, int64_t max_entries, int32_t max_slots);
+
+/* max_vertices >= 1, 0 <= max_entries < 2^31, max_slots >= 1 resident graphs.
+ * opts (NULL: defaults): frontier_tau picks dense or sparse per graph and
+ * step; validate = 1 makes submit check every row pointer and column id on
+ * the host (otherwise only row_ptr[0] and row_ptr[n], and the caller
+ * guarantees a valid symmetric CSR).  FASTSV_ENOMEM if the pool cannot be
+ * allocated. */
+int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entries, int32_t max_slots,
+                         hipStream_t stream, const fastsv_opts *opts, fastsv_server **out);
+void fastsv_server_destroy(fastsv_server *srv);
+
+/* Queue a request: n vertices, nnz entries of a symmetric CSR in HOST memory
+ * (page-locked memory makes the admission copy a plain DMA).  The arrays are
+ * copied to the device at admission, so
+ * h_row_ptr, h_col, h_labels_out (n ints) and h_iters_out (may be NULL) must
+ * stay valid until the ticket is reported done.
+ * FASTSV_ERANGE for a malformed CSR (see opts.validate); FASTSV_ENOMEM if the
+ * graph can never fit the pool. */
+int fastsv_server_submit(fastsv_server *srv, int32_t n, int64_t nnz, const int32_t *h_row_ptr,
+                         const int32_t *h_col_idx, int32_t *h_labels_out, int32_t *h_iters_out,
+                         uint64_t *ticket);
+
+/* Admit what fits, run one iteration for all resident graphs, retire the
+ * converged ones.  Reports how many graphs are resident and queued after it. */
+int fastsv_server_step(fastsv_server *srv, int32_t *n_resident, int32_t *n_queued);
+
+/* Up to cap tickets completed since the last poll, oldest first. */
+int fastsv_server_poll(fastsv_server *srv, uint64_t *done, int32_t cap, int32_t *n_done);
+
+int fastsv_server_get_stats(const fastsv_server *srv, fastsv_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

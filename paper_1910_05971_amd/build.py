@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 HIP_LIB = os.path.join(LIBDIR, "libfastsv.so")
 GEN_LIB = os.path.join(LIBDIR, "libfastsv_gen.so")
 
-HIP_SOURCES = ["fastsv.hip"]
+HIP_SOURCES = ["fastsv.hip", "server.hip"]
 
 # Packed-FP32 instructions are switched off for all device code; the solver
 # itself is integer-only, the flag keeps any float helper scalar.

@@ -50,6 +50,14 @@ struct Counters {
 
 constexpr int kMaxBlocks = 64;
 
+// A graph entering or leaving the serving pool (see server.hip).
+struct SrvNew {
+    int vb, eb, n, nnz;  // pool vertex base, pool entry base, vertices, entries
+    int s_rp, s_col;     // offsets of its row_ptr / col in the staging buffer
+    int tile_base;       // first tile of its dense first iteration
+    int pad;
+};
+
 // Exclusive-scan geometry.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -73,6 +81,15 @@ inline int grid_for(int64_t items, int per_block, int cap = 1 << 30) {
     return (int)g;
 }
 
+}  // namespace fsv
+
+struct fastsv_ctx;
+
+namespace fsv {
+
+// device of a library context (defined in fastsv.hip)
+int ctx_device(const fastsv_ctx *ctx);
+
 // ---- launch wrappers (defined in fastsv.hip) ----
 enum DenseMode : int { kDenseIota = 0, kDenseGather = 1, kDenseBaseIota = 2, kDenseBaseGather = 3 };
 
@@ -85,8 +102,31 @@ void launch_dense(hipStream_t s, int mode, const Tile *tiles, int ntiles, const 
                   const int *vbase, const int *F, int *Fn, const int *G, int *M);
 void launch_sparse(hipStream_t s, const int *frontier, const int *eoff, int fcnt, int edges, const int *rp,
                    const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M);
+// the same with the frontier size read on the device from `counts`; frontier
+// vertices v with skip_mark[vbase[v]] == skip_val are not pushed
+void launch_sparse_dev(hipStream_t s, const IterCounters *counts, int max_blocks, const int *frontier,
+                       const int *eoff, const int *rp, const int *col, const int *vbase, const int *F, int *Fn,
+                       const int *G, int *M, const int *skip_mark, int skip_val);
 void launch_zero_iter(hipStream_t s, IterCounters *ic);
+// lastk (nullable): iteration of the last change per vertex, or per graph at
+// index vbase[u] when vbase is given; gedge (nullable, needs vbase): frontier
+// degree sum per graph at index vbase[u]
 void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
-                        int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter);
+                        int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter,
+                        const int *vbase = nullptr, int *gedge = nullptr);
+void launch_fill(hipStream_t s, int n, int *x, int v);
+
+// serving pool helpers
+void launch_srv_status(hipStream_t s, int nslots, const int *slot_vb, const int *lastk, int step, int *gedge,
+                       int *out_flag, int *out_edges);
+void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
+                            const Tile *pool_tiles, Tile *step_tiles, int *mark, int step);
+void launch_srv_place(hipStream_t s, int nnew, int64_t items, const SrvNew *desc, const int *item_off,
+                      const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
+                      int *lastk);
+void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,
+                      Tile *tiles);
+void launch_srv_retire(hipStream_t s, int nret, int rows, const SrvNew *desc, const int *row_off, int *out, int *F0,
+                       int *F1, int *G, int *M, int *lastk);
 
 }  // namespace fsv

@@ -210,12 +210,26 @@ void launch_sparse(hipStream_t s, const int *frontier, const int *eoff, int fcnt
                    const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M) {
     if (edges <= 0) return;
     const dim3 grid(grid_for(edges, kPushSlots)), block(kPushThreads);
+    const IterCounters *none = nullptr;
+    const int *no_skip = nullptr;
     if (vbase)
-        hipLaunchKernelGGL(k_hook_sparse<true>, grid, block, 0, s, frontier, eoff, fcnt, edges, rp, col, vbase, F, Fn,
-                           G, M);
+        hipLaunchKernelGGL(k_hook_sparse<true>, grid, block, 0, s, frontier, eoff, fcnt, edges, none, rp, col, vbase,
+                           F, Fn, G, M, no_skip, 0);
     else
-        hipLaunchKernelGGL(k_hook_sparse<false>, grid, block, 0, s, frontier, eoff, fcnt, edges, rp, col, vbase, F,
-                           Fn, G, M);
+        hipLaunchKernelGGL(k_hook_sparse<false>, grid, block, 0, s, frontier, eoff, fcnt, edges, none, rp, col, vbase,
+                           F, Fn, G, M, no_skip, 0);
+}
+
+void launch_sparse_dev(hipStream_t s, const IterCounters *counts, int max_blocks, const int *frontier,
+                       const int *eoff, const int *rp, const int *col, const int *vbase, const int *F, int *Fn,
+                       const int *G, int *M, const int *skip_mark, int skip_val) {
+    const dim3 grid(max_blocks > 0 ? max_blocks : 1), block(kPushThreads);
+    if (vbase)
+        hipLaunchKernelGGL(k_hook_sparse<true>, grid, block, 0, s, frontier, eoff, 0, 0, counts, rp, col, vbase, F,
+                           Fn, G, M, skip_mark, skip_val);
+    else
+        hipLaunchKernelGGL(k_hook_sparse<false>, grid, block, 0, s, frontier, eoff, 0, 0, counts, rp, col, vbase, F,
+                           Fn, G, M, skip_mark, skip_val);
 }
 
 void launch_zero_iter(hipStream_t s, IterCounters *ic) {
@@ -223,10 +237,51 @@ void launch_zero_iter(hipStream_t s, IterCounters *ic) {
 }
 
 void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
-                        int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter) {
+                        int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter, const int *vbase,
+                        int *gedge) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_grandparent, dim3(grid_for(n, kGpBlockVerts)), dim3(kGpThreads), 0, s, n, Fn, G, next_fn, rp,
-                       frontier, eoff, ic, write_frontier, lastk, iter);
+                       frontier, eoff, ic, write_frontier, lastk, iter, vbase, gedge);
+}
+
+void launch_fill(hipStream_t s, int n, int *x, int v) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, x, v);
+}
+
+void launch_srv_status(hipStream_t s, int nslots, const int *slot_vb, const int *lastk, int step, int *gedge,
+                       int *out_flag, int *out_edges) {
+    if (nslots <= 0) return;
+    hipLaunchKernelGGL(k_srv_status, dim3(grid_for(nslots, 256)), dim3(256), 0, s, nslots, slot_vb, lastk, step, gedge,
+                       out_flag, out_edges);
+}
+
+void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
+                            const Tile *pool_tiles, Tile *step_tiles, int *mark, int step) {
+    if (ndense <= 0 || total_tiles <= 0) return;
+    hipLaunchKernelGGL(k_srv_dense_tiles, dim3(grid_for(total_tiles, 256, 8192)), dim3(256), 0, s, ndense, desc,
+                       tile_off, pool_tiles, step_tiles, mark, step);
+}
+
+void launch_srv_place(hipStream_t s, int nnew, int64_t items, const SrvNew *desc, const int *item_off,
+                      const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
+                      int *lastk) {
+    if (nnew <= 0 || items <= 0) return;
+    hipLaunchKernelGGL(k_srv_place, dim3(grid_for(items, 256, 8192)), dim3(256), 0, s, nnew, desc, item_off, srcs,
+                       rp, col, F0, F1, G, M, vbase, lastk);
+}
+
+void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,
+                      Tile *tiles) {
+    if (nnew <= 0 || rows <= 0) return;
+    hipLaunchKernelGGL(k_srv_tiles, dim3(grid_for(rows, 256, 8192)), dim3(256), 0, s, nnew, desc, row_off, rp, tiles);
+}
+
+void launch_srv_retire(hipStream_t s, int nret, int rows, const SrvNew *desc, const int *row_off, int *out, int *F0,
+                       int *F1, int *G, int *M, int *lastk) {
+    if (nret <= 0 || rows <= 0) return;
+    hipLaunchKernelGGL(k_srv_retire, dim3(grid_for(rows, 256, 8192)), dim3(256), 0, s, nret, desc, row_off, out, F0,
+                       F1, G, M, lastk);
 }
 
 }  // namespace fsv
@@ -252,6 +307,8 @@ struct fastsv_ctx {
             return FASTSV_EHIP;                                    \
         }                                                          \
     } while (0)
+
+int fsv::ctx_device(const fastsv_ctx *ctx) { return ctx->device; }
 
 namespace {
 
@@ -380,7 +437,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
         launch_zero_iter(stream, ic);
         const bool want_frontier = opts.frontier_tau > 0.0f;
-        launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 1 : 0, P.lastk, it);
+        launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 1 : 0, P.lastk, it,
+                           P.vbase);
         HIP_TRY(hipGetLastError());
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
         HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));

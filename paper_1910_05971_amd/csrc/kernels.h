@@ -646,7 +646,8 @@ __global__ void k_cb_tiles(int nblk, const CbInfo *__restrict__ info, const int 
 __global__ __launch_bounds__(kGpThreads) void k_grandparent(
     int n, const int *__restrict__ Fn, int *__restrict__ G, int *__restrict__ next_fn,
     const int *__restrict__ rp, int *__restrict__ frontier, int *__restrict__ eoff,
-    IterCounters *__restrict__ ctr, int write_frontier, int *__restrict__ lastk, int iter) {
+    IterCounters *__restrict__ ctr, int write_frontier, int *__restrict__ lastk, int iter,
+    const int *__restrict__ vbase, int *__restrict__ gedge) {
     constexpr int kW = kGpThreads / kWave;
     __shared__ int s_cnt[kGpPerThread][kW];
     __shared__ int s_deg[kGpPerThread][kW];
@@ -669,9 +670,30 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
             if (g != old) {
                 G[u] = g;
                 ch[i] = true;
-                if (lastk) lastk[u] = iter;
+                // lastk: iteration of the last change, per vertex, or per graph
+                // (at the graph's first vertex) when the graph bases are given
+                if (lastk) lastk[vbase ? vbase[u] : u] = iter;
                 if (write_frontier) deg[i] = rp[u + 1] - rp[u];
             }
+        }
+    }
+    if (gedge) {
+        // per-graph frontier degree sums (graph bases are nondecreasing over the
+        // consecutive vertices of a wave): one atomic per run of equal bases
+#pragma unroll
+        for (int i = 0; i < kGpPerThread; ++i) {
+            int u = base_u + i * kGpThreads + threadIdx.x;
+            int key = u < n ? vbase[u] : INT_MAX;
+            int v = deg[i];
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                int ov = __shfl_up(v, d, kWave);
+                int ok = __shfl_up(key, d, kWave);
+                if (lane >= d && ok == key) v += ov;
+            }
+            int next_key = __shfl_down(key, 1, kWave);
+            bool tail = lane == kWave - 1 || next_key != key;
+            if (tail && key != INT_MAX && v > 0) atomicAdd(gedge + key, v);
         }
     }
     int rank[kGpPerThread], dpre[kGpPerThread];
@@ -746,65 +768,82 @@ __device__ int wave_upper_search(const int *__restrict__ eoff, int cnt, int s) {
 
 template <bool kHasBase>
 __global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
-    const int *__restrict__ frontier, const int *__restrict__ eoff, int fcnt, int total,
-    const int *__restrict__ rp, const int *__restrict__ col, const int *__restrict__ vbase,
-    const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G, int *__restrict__ M) {
+    const int *__restrict__ frontier, const int *__restrict__ eoff, int fcnt_arg, int total_arg,
+    const IterCounters *__restrict__ counts, const int *__restrict__ rp, const int *__restrict__ col,
+    const int *__restrict__ vbase, const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G,
+    int *__restrict__ M, const int *__restrict__ skip_mark, int skip_val) {
     __shared__ int s_range[2];
     __shared__ int s_off[kPushSlots + 1];
     __shared__ int s_row[kPushSlots + 1];
     __shared__ int s_val[kPushSlots + 1];
     __shared__ int s_base[kHasBase ? kPushSlots + 1 : 1];
-    const int s0 = blockIdx.x * kPushSlots;
-    const int s1 = min(s0 + kPushSlots, total);
-    if (threadIdx.x < kWave) {
-        int i0 = wave_upper_search(eoff, fcnt, s0);
-        int i1 = wave_upper_search(eoff, fcnt, s1 - 1);
-        if (threadIdx.x == 0) { s_range[0] = i0; s_range[1] = i1; }
+    // frontier size from the arguments, or from the counters the grandparent
+    // pass left on the device (then the grid is a fixed size and loops)
+    int fcnt = fcnt_arg, total = total_arg;
+    if (counts) {
+        const unsigned long long pk = counts->packed;
+        fcnt = (int)(pk >> 32);
+        total = (int)(pk & 0xffffffffull);
     }
-    __syncthreads();
-    const int i0 = s_range[0], i1 = s_range[1];
-    // every frontier vertex with edges owns >= 1 slot, so a block's slots touch at
-    // most kPushSlots of them; vertices without edges (possible only when the
-    // matrix is not symmetric) can make the range longer, then the block
-    // searches the offsets in global memory instead
-    const int nv = i1 - i0 + 1;
-    const bool in_lds = nv <= kPushSlots + 1;
-    if (in_lds) {
-        for (int i = threadIdx.x; i < nv; i += kPushThreads) {
-            int v = frontier[i0 + i];
-            s_off[i] = eoff[i0 + i];
-            s_row[i] = rp[v];
-            s_val[i] = G[v];
-            if (kHasBase) s_base[i] = vbase[v];
+    for (int chunk = blockIdx.x; (int64_t)chunk * kPushSlots < total; chunk += gridDim.x) {
+        const int s0 = chunk * kPushSlots;
+        const int s1 = min(s0 + kPushSlots, total);
+        __syncthreads();  // LDS of the previous chunk no longer in use
+        if (threadIdx.x < kWave) {
+            int i0 = wave_upper_search(eoff, fcnt, s0);
+            int i1 = wave_upper_search(eoff, fcnt, s1 - 1);
+            if (threadIdx.x == 0) { s_range[0] = i0; s_range[1] = i1; }
         }
-    }
-    __syncthreads();
-    for (int s = s0 + threadIdx.x; s < s1; s += kPushThreads) {
-        // frontier entry owning slot s: the last i with eoff[i] <= s
-        int lo = 0, hi = nv - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            int om = in_lds ? s_off[mid] : eoff[i0 + mid];
-            if (om <= s) lo = mid;
-            else hi = mid - 1;
-        }
-        int off, row, val, vb = 0;
+        __syncthreads();
+        const int i0 = s_range[0], i1 = s_range[1];
+        // every frontier vertex with edges owns >= 1 slot, so a chunk's slots touch at
+        // most kPushSlots of them; vertices without edges (possible only when the
+        // matrix is not symmetric) can make the range longer, then the block
+        // searches the offsets in global memory instead
+        const int nv = i1 - i0 + 1;
+        const bool in_lds = nv <= kPushSlots + 1;
         if (in_lds) {
-            off = s_off[lo]; row = s_row[lo]; val = s_val[lo];
-            if (kHasBase) vb = s_base[lo];
-        } else {
-            int v = frontier[i0 + lo];
-            off = eoff[i0 + lo]; row = rp[v]; val = G[v];
-            if (kHasBase) vb = vbase[v];
+            for (int i = threadIdx.x; i < nv; i += kPushThreads) {
+                int v = frontier[i0 + i];
+                s_off[i] = eoff[i0 + i];
+                s_row[i] = rp[v];
+                // a vertex whose graph runs the dense pass in this step pushes nothing
+                s_val[i] = (kHasBase && skip_mark && skip_mark[vbase[v]] == skip_val) ? INT_MAX : G[v];
+                if (kHasBase) s_base[i] = vbase[v];
+            }
         }
-        int u = col[row + (s - off)] + vb;
-        int old = atomicMin(M + u, val);
-        if (val < old) {
-            int gu = G[u];
-            if (val < gu) {
-                atomicMin(Fn + u, val);
-                int x = F[u];
-                if (x != u) atomicMin(Fn + x, val);
+        __syncthreads();
+        for (int s = s0 + threadIdx.x; s < s1; s += kPushThreads) {
+            // frontier entry owning slot s: the last i with eoff[i] <= s
+            int lo = 0, hi = nv - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                int om = in_lds ? s_off[mid] : eoff[i0 + mid];
+                if (om <= s) lo = mid;
+                else hi = mid - 1;
+            }
+            int off, row, val, vb = 0;
+            if (in_lds) {
+                off = s_off[lo]; row = s_row[lo]; val = s_val[lo];
+                if (kHasBase) vb = s_base[lo];
+            } else {
+                int v = frontier[i0 + lo];
+                off = eoff[i0 + lo]; row = rp[v]; val = G[v];
+                if (kHasBase) {
+                    vb = vbase[v];
+                    if (skip_mark && skip_mark[vb] == skip_val) val = INT_MAX;
+                }
+            }
+            if (val == INT_MAX) continue;
+            int u = col[row + (s - off)] + vb;
+            int old = atomicMin(M + u, val);
+            if (val < old) {
+                int gu = G[u];
+                if (val < gu) {
+                    atomicMin(Fn + u, val);
+                    int x = F[u];
+                    if (x != u) atomicMin(Fn + x, val);
+                }
             }
         }
     }
@@ -913,24 +952,135 @@ __global__ void k_batch_bases(int ngraphs, const int *__restrict__ vtx_off, int 
 __global__ void k_batch_finish(int ngraphs, const int *__restrict__ vtx_off, const int *__restrict__ src,
                                const int *__restrict__ lastk, int *__restrict__ labels, int *__restrict__ iters,
                                int final_iter, int capped) {
-    __shared__ int s_max[16];
     const int g = blockIdx.x;
     if (g >= ngraphs) return;
     const int v0 = vtx_off[g], v1 = vtx_off[g + 1];
-    int mx = 0;
-    for (int u = v0 + (int)threadIdx.x; u < v1; u += blockDim.x) {
-        labels[u] = src[u] - v0;
-        mx = max(mx, lastk[u]);
-    }
-    for (int d = kWave / 2; d > 0; d >>= 1) mx = max(mx, __shfl_down(mx, d, kWave));
-    const int wave = threadIdx.x / kWave;
-    if (lane_id() == 0) s_max[wave] = mx;
-    __syncthreads();
+    for (int u = v0 + (int)threadIdx.x; u < v1; u += blockDim.x) labels[u] = src[u] - v0;
     if (threadIdx.x == 0) {
-        int m = 0;
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = max(m, s_max[w]);
+        // lastk[v0] holds the last iteration in which a grandparent of graph g changed
+        const int m = v1 > v0 ? lastk[v0] : 0;
         // an empty graph needs no iteration (the solo call returns at once)
         iters[g] = v1 == v0 ? 0 : ((capped && m == final_iter) ? -1 : m + 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Serving pool.  A resident graph owns the pool vertices [vb, vb+n] (the extra
+// vertex n only carries row_ptr[vb+n] = the graph's entry end) and the pool
+// entries [eb, eb+nnz); ids in f and gf are pool-global.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_owner(const int *__restrict__ off, int count, int64_t x) {
+    int lo = 0, hi = count - 1;  // last k with off[k] <= x
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Per resident graph (pool base slot_vb[k]): changed in this step?  and the
+// total degree of its frontier, which is then reset for the next step.
+__global__ void k_srv_status(int nslots, const int *__restrict__ slot_vb, const int *__restrict__ lastk, int step,
+                             int *__restrict__ gedge, int *__restrict__ out_flag, int *__restrict__ out_edges) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nslots) return;
+    const int vb = slot_vb[k];
+    out_flag[k] = lastk[vb] == step;
+    out_edges[k] = gedge[vb];
+    gedge[vb] = 0;
+}
+
+// Tiles of the graphs that run the dense pass in this step, copied from their
+// resident tile ranges into one array; their graphs are marked for the push to
+// skip.  desc[k]: tile_base = first resident tile, s_rp = tile count,
+// s_col = offset in the step array; vb = graph base.
+__global__ void k_srv_dense_tiles(int ndense, const SrvNew *__restrict__ desc, const int *__restrict__ tile_off,
+                                  const Tile *__restrict__ pool_tiles, Tile *__restrict__ step_tiles,
+                                  int *__restrict__ mark, int step) {
+    const int total = tile_off[ndense];
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
+        const int k = find_owner(tile_off, ndense, x);
+        const SrvNew d = desc[k];
+        const int i = x - tile_off[k];
+        step_tiles[x] = pool_tiles[d.tile_base + i];
+        if (i == 0) mark[d.vb] = step;
+    }
+}
+
+// Batched admission.  For new graph k (descriptor SrvNew), staged CSR in
+// `stage` (row_ptr at s_rp, col at s_col, both local) goes to the pool:
+// row_ptr rebased to the pool entry base, col copied, and the vertex state of
+// [vb, vb+n] set to its neutral start (f = gf = mngf = global id).  Work items
+// are numbered across the batch; item_off is the exclusive prefix of the
+// per-graph item counts (2(n+1) + nnz).
+
+__global__ void k_srv_place(int nnew, const SrvNew *__restrict__ desc, const int *__restrict__ item_off,
+                            const int *const *__restrict__ srcs, int *__restrict__ rp, int *__restrict__ col,
+                            int *__restrict__ F0, int *__restrict__ F1, int *__restrict__ G, int *__restrict__ M,
+                            int *__restrict__ vbase, int *__restrict__ lastk) {
+    // srcs[2k], srcs[2k+1]: device-visible row_ptr and col of new graph k
+    // (device staging, or page-locked host memory read directly)
+    const int64_t total = item_off[nnew];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int k = find_owner(item_off, nnew, x);
+        const SrvNew d = desc[k];
+        int i = (int)(x - item_off[k]);
+        if (i <= d.n) {
+            rp[d.vb + i] = srcs[2 * k][i] + d.eb;
+        } else if (i <= 2 * d.n + 1) {
+            i -= d.n + 1;
+            const int u = d.vb + i;
+            F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
+            vbase[u] = d.vb;
+            lastk[u] = 0;
+        } else {
+            i -= 2 * (d.n + 1);
+            col[d.eb + i] = srcs[2 * k + 1][i];
+        }
+    }
+}
+
+// Tiles of the newly admitted graphs for their dense first iteration; rows
+// numbered across the batch (row_off = exclusive prefix of n).
+__global__ void k_srv_tiles(int nnew, const SrvNew *__restrict__ desc, const int *__restrict__ row_off,
+                            const int *__restrict__ rp, Tile *__restrict__ tiles) {
+    const int total = row_off[nnew];
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
+        const int k = find_owner(row_off, nnew, x);
+        const SrvNew d = desc[k];
+        const int r = d.vb + (x - row_off[k]);
+        const int s = rp[r] - d.eb, e = rp[r + 1] - d.eb;
+        if (s >= e) continue;
+        Tile *tb = tiles + d.tile_base;
+        for (int t = s / kTileEntries; t <= (e - 1) / kTileEntries; ++t) {
+            int t0 = t * kTileEntries;
+            int last = min(t0 + kTileEntries, d.nnz) - 1;
+            if (t0 >= s && t0 < e) {
+                tb[t].e0 = d.eb + t0;
+                tb[t].e1 = d.eb + last + 1;
+                tb[t].r_lo = r;
+            }
+            if (last >= s && last < e) tb[t].r_hi = r;
+        }
+    }
+}
+
+// Retirement: local labels of finished graphs into the staging buffer (at
+// s_rp of their descriptor) and their vertex range back to the neutral state.
+__global__ void k_srv_retire(int nret, const SrvNew *__restrict__ desc, const int *__restrict__ row_off,
+                             int *__restrict__ out, int *__restrict__ F0, int *__restrict__ F1, int *__restrict__ G,
+                             int *__restrict__ M, int *__restrict__ lastk) {
+    const int total = row_off[nret];
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
+        const int k = find_owner(row_off, nret, x);
+        const SrvNew d = desc[k];
+        const int i = x - row_off[k];  // 0 .. n (n is the extra vertex)
+        const int u = d.vb + i;
+        if (i < d.n) out[d.s_rp + i] = G[u] - d.vb;
+        F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
+        lastk[u] = 0;
     }
 }
 

@@ -1,0 +1,553 @@
+// Continuous-batching server for connected-components requests.
+//
+// Resident graphs share one device pool and advance together: every step is
+// one iteration of Algorithm 3 (dense pull over the resident graphs' tiles or
+// sparse push over the frontier, then the grandparent pass) for all of them.
+// A graph admitted at step s runs its first iteration in step s; it retires
+// after the first step in which none of its grandparents changed (the
+// termination test of Sec. 3.4 applied to that graph alone).  Ids in f and gf
+// are pool-global, so resident graphs never exchange values and each one
+// follows exactly the iterates it would follow when solved alone.
+//
+// Admission is first-come first-served and by footprint: a request waits
+// until a slot, n+1 pool vertices and nnz pool entries are free.
+//
+// One step, all on the server's stream with a single host synchronisation:
+//   1. graphs found converged by the previous step: labels out to staging,
+//      vertex range back to the neutral state (one launch for all of them)
+//   2. admission: the staged CSRs of the admitted graphs are copied once and
+//      placed into the pool by one launch; their tiles are built
+//   3. hooking, decided per graph: the dense pull over the graph's resident
+//      tiles in its first iteration and whenever its frontier (total degree of
+//      the grandparents that changed in the previous step) exceeds
+//      frontier_tau * nnz; otherwise the sparse push from its frontier (the
+//      push skips the graphs that run dense; frontier size read on the device)
+//   4. grandparent pass over the pool, per graph: changed or not, and the
+//      degree sum of its new frontier.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "engine.h"
+#include "fastsv.h"
+
+using namespace fsv;
+
+namespace {
+
+// First-fit allocator over [0, cap) with coalescing of freed ranges.
+class RangeAlloc {
+public:
+    explicit RangeAlloc(int64_t cap = 0) { reset(cap); }
+    void reset(int64_t cap) {
+        free_.clear();
+        cap_ = cap;
+        if (cap > 0) free_[0] = cap;
+    }
+    int64_t alloc(int64_t len) {
+        if (len <= 0) return 0;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                int64_t start = it->first, rest = it->second - len;
+                free_.erase(it);
+                if (rest > 0) free_[start + len] = rest;
+                return start;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t start, int64_t len) {
+        if (len <= 0) return;
+        auto it = free_.emplace(start, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t capacity() const { return cap_; }
+
+private:
+    std::map<int64_t, int64_t> free_;
+    int64_t cap_ = 0;
+};
+
+struct Request {
+    uint64_t ticket;
+    int n;
+    int64_t nnz;
+    const int32_t *rp, *col;    // caller's host arrays, read at admission
+    const int32_t *drp, *dcol;  // the same as device-visible addresses (page-locked memory), or null
+    int32_t *labels_out;
+    int32_t *iters_out;
+};
+
+enum SlotState : int { kFree = 0, kRunning = 1, kRetiring = 2 };
+
+struct Slot {
+    int state = kFree;
+    uint64_t ticket = 0;
+    int n = 0;
+    int64_t nnz = 0;
+    int vb = 0, eb = 0, tb = 0, ntiles = 0;
+    int64_t fedge = 0;  // frontier degree sum after its last iteration
+    int admit_step = 0, done_step = 0;
+    int32_t *labels_out = nullptr;
+    int32_t *iters_out = nullptr;
+};
+
+inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct PoolLayout {
+    size_t rp, col, F0, F1, G, M, vbase, lastk, frontier, eoff, tiles, ctr, slot_vb, slot_n, flags, stage, desc,
+        off_a, off_b, out, desc_ret, off_ret, step_tiles, gmode, gedge, out_edges, desc_dense, off_dense, srcs,
+        total;
+};
+
+// T: tiles of one step's new graphs; the staging buffer holds the row_ptr and
+// col of all graphs admitted in one step (at most V + E ints) and the labels
+// of all graphs retired in one step (at most V ints).
+PoolLayout pool_layout(int64_t V, int64_t E, int64_t T, int64_t S) {
+    PoolLayout L{};
+    size_t p = 0;
+    auto take = [&](size_t b) { size_t o = p; p += a256(b > 0 ? b : 1); return o; };
+    const size_t v4 = sizeof(int) * (size_t)V;
+    L.rp = take(sizeof(int) * (size_t)(V + 1));
+    L.col = take(sizeof(int) * (size_t)E);
+    L.F0 = take(v4);
+    L.F1 = take(v4);
+    L.G = take(v4);
+    L.M = take(v4);
+    L.vbase = take(v4);
+    L.lastk = take(v4);
+    L.frontier = take(v4);
+    L.eoff = take(v4);
+    L.tiles = take(sizeof(Tile) * (size_t)T);
+    L.ctr = take(sizeof(Counters));
+    L.slot_vb = take(sizeof(int) * (size_t)S);
+    L.slot_n = take(sizeof(int) * (size_t)S);
+    L.flags = take(sizeof(int) * (size_t)S);
+    L.stage = take(sizeof(int) * (size_t)(V + 1 + E));
+    L.desc = take(sizeof(SrvNew) * (size_t)S);
+    L.off_a = take(sizeof(int) * (size_t)(S + 1));
+    L.off_b = take(sizeof(int) * (size_t)(S + 1));
+    L.out = take(v4);
+    L.desc_ret = take(sizeof(SrvNew) * (size_t)S);
+    L.off_ret = take(sizeof(int) * (size_t)(S + 1));
+    L.step_tiles = take(sizeof(Tile) * (size_t)T);
+    L.gmode = take(v4);
+    L.gedge = take(v4);
+    L.out_edges = take(sizeof(int) * (size_t)S);
+    L.desc_dense = take(sizeof(SrvNew) * (size_t)S);
+    L.off_dense = take(sizeof(int) * (size_t)(S + 1));
+    L.srcs = take(sizeof(void *) * (size_t)(2 * S));
+    L.total = p;
+    return L;
+}
+
+}  // namespace
+
+struct fastsv_server {
+    fastsv_ctx *ctx = nullptr;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    fastsv_opts opts{};
+    int64_t V = 0, E = 0, T = 0;
+    int S = 0;
+    char *pool = nullptr;
+    PoolLayout L{};
+    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *slot_vb, *slot_n, *flags, *stage, *off_a, *off_b,
+        *out, *off_ret, *gmode, *gedge, *out_edges, *off_dense;
+    SrvNew *desc, *desc_ret, *desc_dense;
+    const int **srcs;
+    Tile *tiles, *step_tiles;
+    Counters *ctr;
+    // pinned host mirrors
+    int *h_slot_vb = nullptr, *h_slot_n = nullptr, *h_flags = nullptr, *h_off_a = nullptr,
+        *h_off_b = nullptr, *h_out = nullptr, *h_off_ret = nullptr, *h_edges = nullptr, *h_off_dense = nullptr;
+    SrvNew *h_desc = nullptr, *h_desc_ret = nullptr, *h_desc_dense = nullptr;
+    const int **h_srcs = nullptr;
+    RangeAlloc va, ea, ta;
+    std::deque<Request> queue;
+    std::vector<Slot> slots;
+    std::vector<int> flag_slot;  // slot of each entry of h_flags
+    std::deque<uint64_t> done;
+    int step = 0;
+    uint64_t next_ticket = 1;
+    fastsv_server_stats st{};
+};
+
+#define SRV_TRY(expr)                                              \
+    do {                                                           \
+        hipError_t _e = (expr);                                    \
+        if (_e != hipSuccess) {                                    \
+            if (getenv("FASTSV_DEBUG"))                            \
+                fprintf(stderr, "fastsv server: %s failed: %s\n",   \
+                        #expr, hipGetErrorString(_e));             \
+            return FASTSV_EHIP;                                    \
+        }                                                          \
+    } while (0)
+
+namespace {
+
+// Device address of page-locked host memory, or null for pageable memory.
+const int32_t *device_view(const int32_t *h) {
+    if (!h) return nullptr;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, h) != hipSuccess) {
+        (void)hipGetLastError();  // pageable memory: clear the error, copy instead
+        return nullptr;
+    }
+    if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+    return static_cast<const int32_t *>(a.devicePointer);
+}
+
+template <typename T>
+bool pinned(T **p, size_t count) {
+    return hipHostMalloc(reinterpret_cast<void **>(p), sizeof(T) * (count > 0 ? count : 1), hipHostMallocDefault) ==
+           hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fastsv_server_pool_bytes(int32_t max_vertices, int64_t max_entries, int32_t max_slots) {
+    if (max_vertices <= 0 || max_entries < 0 || max_slots <= 0 || max_entries > INT32_MAX - kTileEntries ||
+        (int64_t)max_vertices + 1 + max_entries > INT32_MAX)
+        return 0;
+    const int64_t T = max_entries / kTileEntries + max_slots;
+    return pool_layout(max_vertices, max_entries, T, max_slots).total;
+}
+
+int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entries, int32_t max_slots,
+                         hipStream_t stream, const fastsv_opts *opts, fastsv_server **out) {
+    if (!out) return FASTSV_EINVAL;
+    *out = nullptr;
+    if (!ctx || max_vertices <= 0 || max_entries < 0 || max_slots <= 0) return FASTSV_EINVAL;
+    if (max_entries > INT32_MAX - kTileEntries || (int64_t)max_vertices + 1 + max_entries > INT32_MAX)
+        return FASTSV_EOVERFLOW;
+    fastsv_server *s = new (std::nothrow) fastsv_server();
+    if (!s) return FASTSV_ENOMEM;
+    s->ctx = ctx;
+    s->device = ctx_device(ctx);
+    s->stream = stream;
+    s->opts = opts ? *opts : fastsv_default_opts();
+    if (!(s->opts.frontier_tau >= 0.0f)) { delete s; return FASTSV_EINVAL; }
+    s->V = max_vertices;
+    s->E = max_entries;
+    s->T = max_entries / kTileEntries + max_slots;
+    s->S = max_slots;
+    s->L = pool_layout(s->V, s->E, s->T, s->S);
+    if (hipSetDevice(s->device) != hipSuccess) { delete s; return FASTSV_EHIP; }
+    if (hipMalloc(reinterpret_cast<void **>(&s->pool), s->L.total) != hipSuccess) { delete s; return FASTSV_ENOMEM; }
+    char *p = s->pool;
+    s->rp = reinterpret_cast<int *>(p + s->L.rp);
+    s->col = reinterpret_cast<int *>(p + s->L.col);
+    s->F[0] = reinterpret_cast<int *>(p + s->L.F0);
+    s->F[1] = reinterpret_cast<int *>(p + s->L.F1);
+    s->G = reinterpret_cast<int *>(p + s->L.G);
+    s->M = reinterpret_cast<int *>(p + s->L.M);
+    s->vbase = reinterpret_cast<int *>(p + s->L.vbase);
+    s->lastk = reinterpret_cast<int *>(p + s->L.lastk);
+    s->frontier = reinterpret_cast<int *>(p + s->L.frontier);
+    s->eoff = reinterpret_cast<int *>(p + s->L.eoff);
+    s->tiles = reinterpret_cast<Tile *>(p + s->L.tiles);
+    s->ctr = reinterpret_cast<Counters *>(p + s->L.ctr);
+    s->slot_vb = reinterpret_cast<int *>(p + s->L.slot_vb);
+    s->slot_n = reinterpret_cast<int *>(p + s->L.slot_n);
+    s->flags = reinterpret_cast<int *>(p + s->L.flags);
+    s->stage = reinterpret_cast<int *>(p + s->L.stage);
+    s->desc = reinterpret_cast<SrvNew *>(p + s->L.desc);
+    s->off_a = reinterpret_cast<int *>(p + s->L.off_a);
+    s->off_b = reinterpret_cast<int *>(p + s->L.off_b);
+    s->out = reinterpret_cast<int *>(p + s->L.out);
+    s->desc_ret = reinterpret_cast<SrvNew *>(p + s->L.desc_ret);
+    s->off_ret = reinterpret_cast<int *>(p + s->L.off_ret);
+    s->step_tiles = reinterpret_cast<Tile *>(p + s->L.step_tiles);
+    s->gmode = reinterpret_cast<int *>(p + s->L.gmode);
+    s->gedge = reinterpret_cast<int *>(p + s->L.gedge);
+    s->out_edges = reinterpret_cast<int *>(p + s->L.out_edges);
+    s->desc_dense = reinterpret_cast<SrvNew *>(p + s->L.desc_dense);
+    s->off_dense = reinterpret_cast<int *>(p + s->L.off_dense);
+    s->srcs = reinterpret_cast<const int **>(p + s->L.srcs);
+    // every host buffer below is the source or target of an asynchronous copy
+    // and is written at most once per step
+    bool ok = pinned(&s->h_out, (size_t)s->V) && pinned(&s->h_desc_ret, max_slots) &&
+              pinned(&s->h_edges, max_slots) && pinned(&s->h_desc_dense, max_slots) &&
+              pinned(&s->h_off_dense, max_slots + 1) && pinned(&s->h_srcs, 2 * (size_t)max_slots) &&
+              pinned(&s->h_off_ret, max_slots + 1) && pinned(&s->h_slot_vb, max_slots) && pinned(&s->h_slot_n, max_slots) && pinned(&s->h_flags, max_slots) &&
+              pinned(&s->h_desc, max_slots) &&
+              pinned(&s->h_off_a, max_slots + 1) && pinned(&s->h_off_b, max_slots + 1);
+    if (!ok) { fastsv_server_destroy(s); return FASTSV_ENOMEM; }
+    s->va.reset(s->V);
+    s->ea.reset(s->E);
+    s->ta.reset(s->T);
+    s->slots.assign(max_slots, Slot{});
+    // neutral state everywhere: every pool vertex its own root, empty rows
+    launch_fill(stream, (int)(s->V + 1), s->rp, 0);
+    launch_init(stream, (int)s->V, s->F[0], s->F[1], s->G, s->M, 0);
+    launch_fill(stream, (int)s->V, s->lastk, 0);
+    launch_fill(stream, (int)s->V, s->vbase, 0);
+    launch_fill(stream, (int)s->V, s->gmode, 0);
+    launch_fill(stream, (int)s->V, s->gedge, 0);
+    launch_zero_iter(stream, &s->ctr->it[0]);
+    launch_zero_iter(stream, &s->ctr->it[1]);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+        fastsv_server_destroy(s);
+        return FASTSV_EHIP;
+    }
+    *out = s;
+    return FASTSV_OK;
+}
+
+void fastsv_server_destroy(fastsv_server *s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->pool) (void)hipFree(s->pool);
+    for (void *h : {(void *)s->h_slot_vb, (void *)s->h_slot_n, (void *)s->h_flags, (void *)s->h_desc, (void *)s->h_off_a, (void *)s->h_off_b, (void *)s->h_out,
+                    (void *)s->h_desc_ret, (void *)s->h_off_ret, (void *)s->h_edges, (void *)s->h_desc_dense,
+                    (void *)s->h_off_dense, (void *)s->h_srcs})
+        if (h) (void)hipHostFree(h);
+    delete s;
+}
+
+int fastsv_server_submit(fastsv_server *s, int32_t n, int64_t nnz, const int32_t *h_row_ptr, const int32_t *h_col,
+                         int32_t *h_labels_out, int32_t *h_iters_out, uint64_t *ticket) {
+    if (!s || n < 0 || nnz < 0 || !h_row_ptr || (nnz > 0 && !h_col) || (n > 0 && !h_labels_out)) return FASTSV_EINVAL;
+    if ((int64_t)n + 1 > s->V || nnz > s->E || (nnz + kTileEntries - 1) / kTileEntries > s->T) return FASTSV_ENOMEM;
+    // with opts.validate, a host-side check of the CSR before it is ever
+    // copied to the device; without it the caller guarantees a valid CSR
+    if (h_row_ptr[0] != 0 || h_row_ptr[n] != nnz) return FASTSV_ERANGE;
+    if (s->opts.validate) {
+        for (int32_t u = 0; u < n; ++u)
+            if (h_row_ptr[u] > h_row_ptr[u + 1]) return FASTSV_ERANGE;
+        for (int64_t e = 0; e < nnz; ++e)
+            if ((uint32_t)h_col[e] >= (uint32_t)n) return FASTSV_ERANGE;
+    }
+    Request r;
+    r.ticket = s->next_ticket++;
+    r.n = n;
+    r.nnz = nnz;
+    r.labels_out = h_labels_out;
+    r.iters_out = h_iters_out;
+    if (ticket) *ticket = r.ticket;
+    s->st.submitted++;
+    if (n == 0) {  // nothing to solve
+        if (h_iters_out) *h_iters_out = 0;
+        s->done.push_back(r.ticket);
+        s->st.completed++;
+        return FASTSV_OK;
+    }
+    r.rp = h_row_ptr;
+    r.col = h_col;
+    r.drp = device_view(h_row_ptr);
+    r.dcol = nnz > 0 ? device_view(h_col) : r.drp;
+    s->queue.push_back(r);
+    return FASTSV_OK;
+}
+
+int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued) {
+    if (!s) return FASTSV_EINVAL;
+    SRV_TRY(hipSetDevice(s->device));
+    hipStream_t st = s->stream;
+    const int step = ++s->step;
+    IterCounters *ic_front = &s->ctr->it[(step + 1) & 1];  // frontier left by the previous step
+    IterCounters *ic = &s->ctr->it[step & 1];
+
+    // 1. retire the graphs found converged by the previous step (their labels
+    //    reach the callers after this step's synchronisation)
+    int nret = 0, ret_rows = 0;
+    std::vector<int> retired;
+    for (int i = 0; i < s->S; ++i) {
+        Slot &sl = s->slots[i];
+        if (sl.state != kRetiring) continue;
+        s->h_desc_ret[nret] = SrvNew{sl.vb, sl.eb, sl.n, (int)sl.nnz, ret_rows, 0, 0, 0};
+        s->h_off_ret[nret] = ret_rows;
+        ret_rows += sl.n + 1;
+        retired.push_back(i);
+        ++nret;
+    }
+    if (nret > 0) {
+        s->h_off_ret[nret] = ret_rows;
+        SRV_TRY(hipMemcpyAsync(s->desc_ret, s->h_desc_ret, sizeof(SrvNew) * nret, hipMemcpyHostToDevice, st));
+        SRV_TRY(hipMemcpyAsync(s->off_ret, s->h_off_ret, sizeof(int) * (nret + 1), hipMemcpyHostToDevice, st));
+        launch_srv_retire(st, nret, ret_rows, s->desc_ret, s->off_ret, s->out, s->F[0], s->F[1], s->G, s->M,
+                          s->lastk);
+        SRV_TRY(hipGetLastError());
+        SRV_TRY(hipMemcpyAsync(s->h_out, s->out, sizeof(int) * (size_t)ret_rows, hipMemcpyDeviceToHost, st));
+        // the ranges can be handed out again: everything below runs after the reset on the stream
+        for (int j = 0; j < nret; ++j) {
+            Slot &sl = s->slots[retired[j]];
+            s->va.release(sl.vb, sl.n + 1);
+            s->ea.release(sl.eb, sl.nnz);
+            s->ta.release(sl.tb, sl.ntiles);
+        }
+    }
+
+    // 2. admission
+    int nnew = 0, new_rows = 0;
+    int64_t items = 0, staged = 0;
+    while (!s->queue.empty()) {
+        int k = -1;
+        for (int i = 0; i < s->S; ++i)
+            if (s->slots[i].state == kFree) { k = i; break; }
+        if (k < 0) break;
+        Request &r = s->queue.front();
+        const int ntiles = (int)((r.nnz + kTileEntries - 1) / kTileEntries);
+        const int64_t vb = s->va.alloc(r.n + 1);
+        if (vb < 0) break;
+        const int64_t eb = s->ea.alloc(r.nnz);
+        if (eb < 0) { s->va.release(vb, r.n + 1); break; }
+        const int64_t tb = s->ta.alloc(ntiles);
+        if (tb < 0) { s->va.release(vb, r.n + 1); s->ea.release(eb, r.nnz); break; }
+        Slot &sl = s->slots[k];
+        sl.state = kRunning;
+        sl.ticket = r.ticket;
+        sl.n = r.n;
+        sl.nnz = r.nnz;
+        sl.vb = (int)vb;
+        sl.eb = (int)eb;
+        sl.tb = (int)tb;
+        sl.ntiles = ntiles;
+        sl.fedge = 0;
+        sl.admit_step = step;
+        sl.labels_out = r.labels_out;
+        sl.iters_out = r.iters_out;
+        SrvNew d{(int)vb, (int)eb, r.n, (int)r.nnz, (int)staged, (int)(staged + r.n + 1), (int)tb, 0};
+        if (r.drp && r.dcol) {
+            // page-locked: the placement kernel reads the host arrays directly
+            s->h_srcs[2 * nnew] = r.drp;
+            s->h_srcs[2 * nnew + 1] = r.dcol;
+        } else {
+            SRV_TRY(hipMemcpyAsync(s->stage + d.s_rp, r.rp, sizeof(int) * (size_t)(r.n + 1), hipMemcpyHostToDevice,
+                                   st));
+            if (r.nnz > 0)
+                SRV_TRY(hipMemcpyAsync(s->stage + d.s_col, r.col, sizeof(int) * (size_t)r.nnz, hipMemcpyHostToDevice,
+                                       st));
+            s->h_srcs[2 * nnew] = s->stage + d.s_rp;
+            s->h_srcs[2 * nnew + 1] = s->stage + d.s_col;
+            staged += r.n + 1 + r.nnz;
+        }
+        s->h_desc[nnew] = d;
+        s->h_off_a[nnew] = (int)items;
+        s->h_off_b[nnew] = new_rows;
+        items += 2 * ((int64_t)r.n + 1) + r.nnz;
+        new_rows += r.n;
+        ++nnew;
+        s->queue.pop_front();
+        s->st.admitted++;
+    }
+    if (nnew > 0) {
+        s->h_off_a[nnew] = (int)items;
+        s->h_off_b[nnew] = new_rows;
+        SRV_TRY(hipMemcpyAsync(s->desc, s->h_desc, sizeof(SrvNew) * nnew, hipMemcpyHostToDevice, st));
+        SRV_TRY(hipMemcpyAsync(s->srcs, s->h_srcs, sizeof(void *) * 2 * nnew, hipMemcpyHostToDevice, st));
+        SRV_TRY(hipMemcpyAsync(s->off_a, s->h_off_a, sizeof(int) * (nnew + 1), hipMemcpyHostToDevice, st));
+        SRV_TRY(hipMemcpyAsync(s->off_b, s->h_off_b, sizeof(int) * (nnew + 1), hipMemcpyHostToDevice, st));
+        launch_srv_place(st, nnew, items, s->desc, s->off_a, s->srcs, s->rp, s->col, s->F[0], s->F[1], s->G, s->M,
+                         s->vbase, s->lastk);
+        launch_srv_tiles(st, nnew, new_rows, s->desc, s->off_b, s->rp, s->tiles);
+        SRV_TRY(hipGetLastError());
+    }
+
+    // 3./4. one iteration for every resident graph
+    int ns = 0, vhigh = 0, ndense = 0, dense_tiles = 0;
+    s->flag_slot.clear();
+    for (int i = 0; i < s->S; ++i) {
+        const Slot &sl = s->slots[i];
+        if (sl.state != kRunning) continue;
+        s->h_slot_vb[ns] = sl.vb;
+        s->flag_slot.push_back(i);
+        vhigh = std::max(vhigh, sl.vb + sl.n + 1);
+        ++ns;
+        const bool dense = sl.admit_step == step ||
+                           (double)sl.fedge > (double)s->opts.frontier_tau * (double)sl.nnz;
+        if (dense && sl.ntiles > 0) {
+            s->h_desc_dense[ndense] = SrvNew{sl.vb, sl.eb, sl.n, (int)sl.nnz, sl.ntiles, dense_tiles, sl.tb, 0};
+            s->h_off_dense[ndense] = dense_tiles;
+            ++ndense;
+            dense_tiles += sl.ntiles;
+        }
+    }
+    launch_zero_iter(st, ic);
+    if (ns > 0) {
+        int *F = s->F[(step + 1) & 1], *Fn = s->F[step & 1];
+        SRV_TRY(hipMemcpyAsync(s->slot_vb, s->h_slot_vb, sizeof(int) * ns, hipMemcpyHostToDevice, st));
+        if (ndense > 0) {
+            s->h_off_dense[ndense] = dense_tiles;
+            SRV_TRY(hipMemcpyAsync(s->desc_dense, s->h_desc_dense, sizeof(SrvNew) * ndense, hipMemcpyHostToDevice, st));
+            SRV_TRY(hipMemcpyAsync(s->off_dense, s->h_off_dense, sizeof(int) * (ndense + 1), hipMemcpyHostToDevice,
+                                   st));
+            launch_srv_dense_tiles(st, ndense, dense_tiles, s->desc_dense, s->off_dense, s->tiles, s->step_tiles,
+                                   s->gmode, step);
+            launch_dense(st, kDenseBaseGather, s->step_tiles, dense_tiles, s->rp, s->col, s->vbase, F, Fn, s->G, s->M);
+            s->st.dense_steps++;
+        }
+        launch_sparse_dev(st, ic_front, 4096, s->frontier, s->eoff, s->rp, s->col, s->vbase, F, Fn, s->G, s->M,
+                          s->gmode, step);
+        s->st.sparse_steps++;
+        launch_grandparent(st, vhigh, Fn, s->G, F, s->rp, s->frontier, s->eoff, ic, 1, s->lastk, step, s->vbase,
+                           s->gedge);
+        launch_srv_status(st, ns, s->slot_vb, s->lastk, step, s->gedge, s->flags, s->out_edges);
+        SRV_TRY(hipGetLastError());
+        SRV_TRY(hipMemcpyAsync(s->h_flags, s->flags, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+        SRV_TRY(hipMemcpyAsync(s->h_edges, s->out_edges, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+    }
+    SRV_TRY(hipStreamSynchronize(st));
+    for (int j = 0; j < nret; ++j) {
+        Slot &sl = s->slots[retired[j]];
+        memcpy(sl.labels_out, s->h_out + s->h_desc_ret[j].s_rp, sizeof(int) * (size_t)sl.n);
+        if (sl.iters_out) *sl.iters_out = sl.done_step - sl.admit_step + 1;
+        s->done.push_back(sl.ticket);
+        s->st.completed++;
+        sl = Slot{};
+    }
+    for (int j = 0; j < ns; ++j) {
+        Slot &sl = s->slots[s->flag_slot[j]];
+        sl.fedge = s->h_edges[j];
+        if (!s->h_flags[j]) {
+            sl.state = kRetiring;  // converged in this step; labels leave at the next step
+            sl.done_step = step;
+        }
+    }
+    s->st.steps++;
+    if (n_resident) *n_resident = ns;
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return FASTSV_OK;
+}
+
+int fastsv_server_poll(fastsv_server *s, uint64_t *done, int32_t cap, int32_t *n_done) {
+    if (!s || cap < 0 || (cap > 0 && !done) || !n_done) return FASTSV_EINVAL;
+    int32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        done[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_done = k;
+    return FASTSV_OK;
+}
+
+int fastsv_server_get_stats(const fastsv_server *s, fastsv_server_stats *out) {
+    if (!s || !out) return FASTSV_EINVAL;
+    *out = s->st;
+    return FASTSV_OK;
+}
+
+}  // extern "C"

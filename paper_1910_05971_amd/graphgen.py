@@ -252,3 +252,46 @@ def c4_batch(num_graphs: int = 4096, max_n: int | None = None) -> Batch:
 
 def num_threads() -> int:
     return int(_load().gg_num_threads())
+
+
+# ---- request streams (serving workload) ----
+
+@dataclasses.dataclass
+class RequestTrace:
+    arrivals: np.ndarray   # seconds after the start, nondecreasing
+    kinds: np.ndarray      # 0 = Erdos-Renyi from the batch distribution, 1 = R-MAT
+    graphs: list           # Graph per request (shared objects from the pools)
+
+
+def request_trace(num_requests: int, rate_per_s: float, seed: int = 5, er_pool: int = 256,
+                  rmat_pool: int = 2, rmat_frac: float = 0.01, rmat_scale: int = 20,
+                  rmat_edge_factor: int = 16) -> RequestTrace:
+    """Poisson arrivals (exponential gaps, output 2i of stream 0) of requests
+    that are R-MAT graphs with probability rmat_frac (output 2i+1 of stream 0)
+    and otherwise Erdos-Renyi graphs from the batch size distribution.  The
+    graphs come from fixed pools (er_pool ER graphs, rmat_pool R-MAT graphs);
+    request i takes pool entry (output i of stream 1) mod the pool size."""
+    ns, ms = batch_sizes(er_pool, seed)
+    ers = []
+    for g in range(er_pool):
+        src, dst = er_edges(int(ns[g]), int(ms[g]), seed, 1000 + g)
+        rp, col = csr_from_edges(int(ns[g]), src, dst)
+        ers.append(Graph(f"req_er{g}", int(ns[g]), rp, col, int(src.shape[0])))
+    rmats = [rmat(rmat_scale, rmat_edge_factor, seed=seed * 100 + k) for k in range(rmat_pool)] if rmat_pool else []
+    arrivals = np.empty(num_requests)
+    kinds = np.empty(num_requests, dtype=np.int32)
+    graphs = []
+    t = 0.0
+    for i in range(num_requests):
+        u = uniform(seed, 0, 2 * i)
+        t += -np.log1p(-u) / rate_per_s
+        arrivals[i] = t
+        is_rmat = rmats and uniform(seed, 0, 2 * i + 1) < rmat_frac
+        pick = rng_at(seed, 1, i)
+        if is_rmat:
+            kinds[i] = 1
+            graphs.append(rmats[pick % len(rmats)])
+        else:
+            kinds[i] = 0
+            graphs.append(ers[pick % len(ers)])
+    return RequestTrace(arrivals, kinds, graphs)

@@ -1,0 +1,117 @@
+"""Continuous-batching server vs the oracle (needs an MI355X).
+
+Every request must get the labels AND the iteration count of its solo run,
+whatever else is resident at the same time."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle_pins as P
+from paper_1910_05971_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    gs = [gg.er(3000, 5000, seed=61), gg.er(20000, 100000, seed=62), gg.rmat(13, 8, seed=63),
+          gg.grid(60, 70, 0.55, seed=64), gg.er(64, 100, seed=65)]
+    rp, col = P.csr_from_pairs(1, [])
+    gs.append(gg.Graph("single", 1, rp, col, 0))
+    rp, col = P.csr_from_pairs(50, [])
+    gs.append(gg.Graph("edgeless", 50, rp, col, 0))
+    rp, col = P.csr_from_pairs(7, [(5, 2), (5, 6), (6, 0)])
+    gs.append(gg.Graph("golden7", 7, rp, col, 3))
+    b = gg.c4_batch(24, max_n=5000)
+    gs += [b.graph(i) for i in range(24)]
+    return gs
+
+
+def _expected(g):
+    lab = O.uf_labels(g.n, g.row_ptr, g.col)
+    its = O.fastsv_alg2(g.n, g.row_ptr, g.col).iterations
+    return lab, its
+
+
+@pytest.mark.parametrize("tau", [0.0, 0.05, 1.0])
+def test_server_matches_solo(gpu_ok, tau):
+    from paper_1910_05971_amd.serving import Server
+    gs = _mix()
+    want = [_expected(g) for g in gs]
+    srv = Server(max_vertices=200_000, max_entries=2_000_000, max_slots=16, frontier_tau=tau)
+    ticket_of = {}
+    got = {}
+    rng = np.random.default_rng(1)
+    pending = list(range(len(gs)))
+    # staggered arrivals: a few new requests before each step
+    while pending or ticket_of:
+        for _ in range(int(rng.integers(0, 4))):
+            if pending:
+                i = pending.pop(0)
+                ticket_of[srv.submit(gs[i].row_ptr, gs[i].col)] = i
+        srv.step()
+        for t, lab, its in srv.poll():
+            got[ticket_of.pop(t)] = (lab.copy(), its)
+    srv.close()
+    for i, g in enumerate(gs):
+        lab, its = got[i]
+        assert np.array_equal(lab, want[i][0]), g.name
+        assert its == want[i][1], (g.name, its, want[i][1])
+
+
+def test_server_small_pool_queues(gpu_ok):
+    from paper_1910_05971_amd.serving import Server
+    gs = [gg.er(5000, 15000, seed=70 + k) for k in range(10)]
+    nnz_max = max(g.nnz for g in gs)
+    srv = Server(max_vertices=2 * 5001 + 10, max_entries=2 * nnz_max + 10, max_slots=4)
+    tickets = {srv.submit(g.row_ptr, g.col): i for i, g in enumerate(gs)}
+    got = {}
+    for _ in range(1000):
+        r, q = srv.step()
+        for t, lab, its in srv.poll():
+            got[tickets[t]] = (lab.copy(), its)
+        if r == 0 and q == 0:
+            break
+    st = srv.stats()
+    srv.close()
+    assert len(got) == 10 and st.admitted == 10 and st.completed == 10
+    for i, g in enumerate(gs):
+        lab, its = _expected(g)
+        assert np.array_equal(got[i][0], lab) and got[i][1] == its
+
+
+def test_server_rejects(gpu_ok):
+    import paper_1910_05971_amd as fs
+    from paper_1910_05971_amd.serving import Server
+    srv = Server(max_vertices=100, max_entries=100, max_slots=2)
+    big = gg.er(500, 600, seed=3)
+    with pytest.raises(fs.FastSVError) as e:
+        srv.submit(big.row_ptr, big.col)
+    assert e.value.status == fs.FASTSV_ENOMEM
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    with pytest.raises(fs.FastSVError) as e:
+        srv.submit(rp, np.array([1, 5], dtype=np.int32))
+    assert e.value.status == fs.FASTSV_ERANGE
+    srv.close()
+
+
+
+
+def test_server_page_locked_requests(gpu_ok):
+    # page-locked request arrays are read by the placement kernel directly
+    from paper_1910_05971_amd.serving import Server, pin_graphs
+    gs = pin_graphs(_mix())
+    srv = Server(max_vertices=200_000, max_entries=2_000_000, max_slots=8, validate=False)
+    tickets = {srv.submit(g.row_ptr, g.col): i for i, g in enumerate(gs)}
+    got = {}
+    for _ in range(10000):
+        r, q = srv.step()
+        for t, lab, its in srv.poll():
+            got[tickets[t]] = (lab.copy(), its)
+        if len(got) == len(gs):
+            break
+    srv.close()
+    for i, g in enumerate(gs):
+        lab, its = _expected(g)
+        assert np.array_equal(got[i][0], lab), g.name
+        assert got[i][1] == its, g.name

@@ -136,3 +136,10 @@ def test_deterministic_across_thread_counts():
         outs.append(subprocess.run([sys.executable, "-c", code], env=env, check=True,
                                    capture_output=True, text=True).stdout.strip())
     assert len(set(outs)) == 1, outs
+
+
+def test_request_trace_shape():
+    tr = gg.request_trace(300, 2000.0, er_pool=16, rmat_pool=1, rmat_scale=10, rmat_edge_factor=4)
+    assert np.all(np.diff(tr.arrivals) >= 0)
+    assert abs(tr.arrivals[-1] - 300 / 2000.0) < 0.05
+    assert tr.kinds.sum() < 15
