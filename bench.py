@@ -1,15 +1,22 @@
 """Benchmark: FastSV connected components on one MI355X.
 
-One step = one complete connected-components solve (every iteration of
-hooking, shortcutting, grandparent and termination test) of the R-MAT
-scale-24 / edge-factor-16 graph (16.8M vertices, 268M undirected edge draws,
-a=.57 b=c=.19 d=.05, permuted ids; seed 2), already resident in HBM.
+Headline (the JSON line's value): one step = one complete connected-components
+solve (every iteration of hooking, shortcutting, grandparent and termination
+test) of the R-MAT scale-24 / edge-factor-16 graph (16.8M vertices, 268M
+undirected edge draws, a=.57 b=c=.19 d=.05, ids permuted; seed 2), already
+resident in HBM; value = undirected edges per second.
 
-Prints one JSON line:
-  value    undirected edges per second per solve (m_eff * steps / time)
-  roofline dense hooking kernel (the dominant one): algorithmic bytes per
-           launch / average launch time from HIP events on its stream, vs 8 TB/s
-  cpu_baseline  the union-find oracle on the host, one core, full graph
+Also in the same JSON line:
+  roofline      the dense gather pass (the dominant kernel): algorithmic bytes
+                per launch / its average launch time from HIP events on the
+                call's stream, against 8 TB/s
+  cpu_baseline  the union-find oracle on the host, one core, the whole graph
+  batched       4096 Erdos-Renyi graphs in one batched call vs one call per
+                graph (graphs/s)
+  serving       Poisson request stream (2000 req/s; 99% graphs from the batch
+                distribution, 1% R-MAT scale 20) through the continuous-
+                batching server vs one request at a time: p50/p99 latency and
+                graphs/s, open loop and at saturation
 """
 from __future__ import annotations
 
@@ -23,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "undirected edges/s per CC solve & % HBM peak; batched graphs/s & p99 vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -33,8 +45,12 @@ def parse():
     ap.add_argument("--workload", default="rmat24", choices=["rmat24", "er65k", "grid4096", "rmat20"])
     ap.add_argument("--tau", type=float, default=None, help="frontier threshold (default: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="counter-measured HBM bytes per dense launch (written from rocprofv3 runs)")
+                    help="counter-measured HBM bytes per launch of the dense gather pass")
     return ap.parse_args()
 
 
@@ -50,6 +66,162 @@ def make_graph(name):
     return gg.c3_grid(), {"workload": "grid_4096x4096_p0.55", "n": 4096 * 4096, "p": 0.55, "seed": 3}
 
 
+def bench_solve(args, fs, torch, np):
+    t0 = time.time()
+    g, cfg = make_graph(args.workload)
+    log(f"generated {cfg['workload']}: n={g.n} nnz={g.nnz} m_eff={g.m_eff} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ws = torch.empty(fs.workspace_bytes(g.n, g.nnz) + 256, dtype=torch.uint8, device=dev)
+    kw = {} if args.tau is None else {"frontier_tau": args.tau}
+    # validate once, outside the timed region
+    fs.cc_csr(rp, col, labels=labels, workspace=ws, validate=True, **kw)
+    for _ in range(args.warmup):
+        fs.cc_csr(rp, col, labels=labels, workspace=ws, **kw)
+    torch.cuda.synchronize()
+    log("timed region")
+    # every kernel is timed with HIP events on the call's stream
+    gather_ms, gather_n, first_ms, sparse_ms, gp_ms = 0.0, 0, 0.0, 0.0, 0.0
+    iters = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = fs.cc_csr(rp, col, labels=labels, workspace=ws, timing=True, **kw)
+        iters.append(st.iterations)
+        for k in range(min(st.iterations, 64)):
+            if st.sparse[k]:
+                sparse_ms += st.ms_hook[k]
+            elif k == 0:
+                first_ms += st.ms_hook[k]
+            else:
+                gather_ms += st.ms_hook[k]
+                gather_n += 1
+            gp_ms += st.ms_gp[k]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    n, nnz = g.n, g.nnz
+    # dense gather pass: row_ptr, col, G[col] gathers, then G, F, M per row
+    bytes_dense = 4 * (n + 1) + 8 * nnz + 12 * n
+    avg_ms = gather_ms / max(gather_n, 1)
+    achieved = bytes_dense / (avg_ms * 1e-3) / 1e9 if gather_n else 0.0
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            traffic = json.load(open(args.traffic_json)).get(cfg["workload"], {}).get("hook_dense_gather_bytes")
+        except Exception:
+            traffic = None
+    res = {
+        "value": g.m_eff * args.steps / elapsed,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "config": dict(cfg, m_eff=g.m_eff, nnz=g.nnz, iterations=iters[-1] if iters else None,
+                       frontier_tau=args.tau),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_tile_reduce<kGather> (dense gather pass)", "alg_bytes_per_launch": bytes_dense,
+                     "avg_launch_ms": avg_ms, "launches": gather_n},
+        "breakdown_ms_per_step": {"first_iteration": first_ms / args.steps, "dense_gather": gather_ms / args.steps,
+                                  "sparse_push": sparse_ms / args.steps, "grandparent": gp_ms / args.steps},
+    }
+    cpu = None
+    check = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (union-find oracle, one core)")
+        reps, t_cpu = 0, 0.0
+        while t_cpu < 10.0 and reps < 5:
+            t1 = time.perf_counter()
+            want = oracle.uf_labels(g.n, g.row_ptr, g.col)
+            t_cpu += time.perf_counter() - t1
+            reps += 1
+        cpu = {"value": g.m_eff * reps / t_cpu, "unit": "undirected edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"union-find oracle over the whole {cfg['workload']} graph, {reps} run(s), "
+                         f"{t_cpu:.1f} s, single thread"}
+        check = bool(np.array_equal(labels.cpu().numpy(), want))
+    res["cpu_baseline"] = cpu
+    res["labels_match_oracle"] = check
+    del rp, col, labels, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_batch(fs, torch, np):
+    from paper_1910_05971_amd import graphgen as gg
+    t0 = time.time()
+    b = gg.c4_batch()
+    log(f"batch: {b.num_graphs} graphs, n={b.row_ptr.shape[0] - 1} nnz={b.col.shape[0]} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    vo, eo, rp, col = [torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+                       for x in (b.vtx_off, b.edge_off, b.row_ptr, b.col)]
+    fs.cc_batch_csr(vo, eo, rp, col, validate=True)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, iters, st = fs.cc_batch_csr(vo, eo, rp, col)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    t_batch = sorted(times)[1]
+    # plain: one cc_csr call per graph on device-resident sub-CSRs
+    subs = []
+    for gi in range(b.num_graphs):
+        s = b.graph(gi)
+        subs.append((torch.from_numpy(np.ascontiguousarray(s.row_ptr)).to(dev),
+                     torch.from_numpy(np.ascontiguousarray(s.col)).to(dev)))
+    for r, c in subs[:64]:
+        fs.cc_csr(r, c)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r, c in subs:
+        fs.cc_csr(r, c)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t
+    return {"workload": "4096 Erdos-Renyi graphs, n log-uniform in [64, 65536), average degree uniform in [2, 32]",
+            "graphs": b.num_graphs, "total_edges_undirected": int(b.m_eff.sum()),
+            "graphs_per_s": b.num_graphs / t_batch, "ms_per_batch": 1000 * t_batch,
+            "iterations": st.iterations, "plain_graphs_per_s": b.num_graphs / t_plain,
+            "speedup_vs_plain": t_plain / t_batch}
+
+
+def bench_serve(args, torch, np):
+    from paper_1910_05971_amd import graphgen as gg, serving
+    t0 = time.time()
+    tr = gg.request_trace(args.serve_requests, args.serve_rate)
+    graphs = serving.pin_graphs(tr.graphs)
+    log(f"serving trace: {len(graphs)} requests ({int(tr.kinds.sum())} R-MAT scale 20) in {time.time() - t0:.1f}s")
+    out = {"workload": f"Poisson {args.serve_rate:.0f} req/s, {len(graphs)} requests: 99% Erdos-Renyi from the "
+                       f"batch distribution, 1% R-MAT scale 20 edge factor 16; host-resident page-locked CSRs",
+           "requests": len(graphs), "rmat_requests": int(tr.kinds.sum())}
+
+    def pct(lat):
+        return float(np.percentile(lat, 50) * 1e3), float(np.percentile(lat, 99) * 1e3)
+
+    def server():
+        return serving.Server(max_vertices=8_000_000, max_entries=150_000_000, max_slots=512, validate=False)
+
+    # warm both paths
+    srv = server()
+    serving.run_open_loop(srv, graphs[:64], np.zeros(64))
+    srv.close()
+    serving.run_plain(graphs[:64], np.zeros(64))
+    for mode, arr in (("open_loop", tr.arrivals), ("saturation", np.zeros_like(tr.arrivals))):
+        srv = server()
+        lat, span, _ = serving.run_open_loop(srv, graphs, arr)
+        s = srv.stats()
+        srv.close()
+        p50, p99 = pct(lat)
+        lat_p, span_p, _ = serving.run_plain(graphs, arr)
+        q50, q99 = pct(lat_p)
+        out[mode] = {"server": {"graphs_per_s": len(graphs) / span, "p50_ms": p50, "p99_ms": p99,
+                                "steps": int(s.steps)},
+                     "plain": {"graphs_per_s": len(graphs) / span_p, "p50_ms": q50, "p99_ms": q99},
+                     "throughput_ratio": span_p / span}
+        log(f"serving {mode}: server {len(graphs) / span:.0f} graphs/s p99 {p99:.2f} ms; "
+            f"plain {len(graphs) / span_p:.0f} graphs/s p99 {q99:.2f} ms")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -60,97 +232,31 @@ def main():
     import torch
     import paper_1910_05971_amd as fs
 
-    t0 = time.time()
-    g, cfg = make_graph(args.workload)
-    print(f"[bench] generated {cfg['workload']}: n={g.n} nnz={g.nnz} m_eff={g.m_eff} "
-          f"in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    dev = torch.device("cuda:0")
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    col = torch.from_numpy(g.col).to(dev)
-    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
-    ws = torch.empty(fs.workspace_bytes(g.n, g.nnz) + 256, dtype=torch.uint8, device=dev)
-    kw = {} if args.tau is None else {"frontier_tau": args.tau}
-    # validate once, outside the timed region
-    _, st = fs.cc_csr(rp, col, labels=labels, workspace=ws, validate=True, **kw)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        fs.cc_csr(rp, col, labels=labels, workspace=ws, **kw)
-    torch.cuda.synchronize()
-    # timed region: every kernel is timed with HIP events on the call's stream
-    hook_ms, hook_n, gp_ms, sparse_ms = 0.0, 0, 0.0, 0.0
-    iters = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = fs.cc_csr(rp, col, labels=labels, workspace=ws, timing=True, **kw)
-        iters.append(st.iterations)
-        for k in range(min(st.iterations, 64)):
-            if st.sparse[k]:
-                sparse_ms += st.ms_hook[k]
-            else:
-                hook_ms += st.ms_hook[k]
-                hook_n += 1
-            gp_ms += st.ms_gp[k]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = 1000.0 * elapsed / args.steps
-    value = g.m_eff * args.steps / elapsed
-
-    # roofline of the dense hooking kernel: algorithmic bytes per launch
-    n, nnz = g.n, g.nnz
-    bytes_dense = 4 * (n + 1) + 8 * nnz + 12 * n
-    avg_ms = hook_ms / max(hook_n, 1)
-    achieved = bytes_dense / (avg_ms * 1e-3) / 1e9 if hook_n else 0.0
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            traffic = tj.get(cfg["workload"], {}).get("hook_dense_bytes")
-        except Exception:
-            traffic = None
-
-    # correctness spot check of the timed output against the oracle (outside the timing)
-    check = None
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        reps, t_cpu = 0, 0.0
-        while t_cpu < 10.0 and reps < 5:
-            t1 = time.perf_counter()
-            want = oracle.uf_labels(g.n, g.row_ptr, g.col)
-            t_cpu += time.perf_counter() - t1
-            reps += 1
-        cpu = {"value": g.m_eff * reps / t_cpu, "unit": "undirected edges/s", "cores": 1, "kind": "oracle",
-               "sample": f"union-find oracle over the whole graph, {reps} run(s), {t_cpu:.1f} s, single thread"}
-        got = labels.cpu().numpy()
-        check = bool(np.array_equal(got, want))
-
+    res = bench_solve(args, fs, torch, np)
     out = {
-        "metric": "undirected edges/s per CC solve",
-        "value": value,
+        "metric": METRIC,
+        "value": res["value"],
         "unit": "undirected edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": dict(cfg, m_eff=g.m_eff, nnz=g.nnz, iterations=iters[-1] if iters else None,
-                       frontier_tau=args.tau),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_hook_dense", "alg_bytes_per_launch": bytes_dense,
-                     "avg_launch_ms": avg_ms, "launches": hook_n},
-        "breakdown_ms_per_step": {"hook_dense": hook_ms / args.steps, "hook_sparse": sparse_ms / args.steps,
-                                  "grandparent": gp_ms / args.steps},
-        "labels_match_oracle": check,
+        "config": res["config"],
+        "roofline": res["roofline"],
+        "breakdown_ms_per_step": res["breakdown_ms_per_step"],
+        "labels_match_oracle": res["labels_match_oracle"],
     }
-    if cpu:
-        out["cpu_baseline"] = cpu
+    if res["cpu_baseline"]:
+        out["cpu_baseline"] = res["cpu_baseline"]
+    if not args.no_batch:
+        out["batched"] = bench_batch(fs, torch, np)
+    if not args.no_serve:
+        out["serving"] = bench_serve(args, torch, np)
     print(json.dumps(out), flush=True)
 
 

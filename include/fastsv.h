@@ -75,7 +75,13 @@ typedef struct {
     int32_t block_shift;    /* log2 of the column-block width in vertices; 0 = automatic (2^19,
                                widened so that there are at most 64 blocks).  4..30 otherwise, and
                                the graph must then have at most 64 blocks. */
-    int32_t reserved[2];
+    int32_t binned;         /* binned dense SpMV: the stored entries are regrouped once per call
+                               by 2^bin_shift-row bins of their column (6 B per entry), and each
+                               dense iteration from the second on reduces a bin in LDS while
+                               gathering gf in ascending order.  1 use it, 0 never, -1 automatic
+                               (the default: graphs with more than 2^22 vertices).  Same iterates
+                               either way; not used when the graph needs more than 2048 bins. */
+    int32_t bin_shift;      /* log2 of the bin width in vertices; 0 = automatic (15); 8..15 */
 } fastsv_opts;
 
 #define FASTSV_TRACE_ITERS 64
@@ -88,6 +94,9 @@ typedef struct {
     int32_t num_tiles;             /* edge tiles of the dense kernel */
     int32_t blocked_prepared;      /* 1 if the column-blocked layout was built in this call */
     int32_t blocked_iterations;    /* dense iterations that ran the column-blocked passes */
+    int32_t binned_iterations;     /* dense iterations that ran the binned passes */
+    int32_t num_bins;              /* bins of the binned layout (0 when it was not built) */
+    float ms_bin_prepare;          /* time to build the binned layout (opts.timing) */
     int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */
     int64_t alg_bytes;             /* algorithmic bytes of all executed iterations (4 B per int32
                                       read or written, each gather counted) */

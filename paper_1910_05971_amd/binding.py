@@ -16,7 +16,8 @@ import threading
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libfastsv.so")
+# FASTSV_LIBRARY selects another build of the same library (same C ABI)
+LIB_PATH = os.environ.get("FASTSV_LIBRARY") or os.path.join(_HERE, "_lib", "libfastsv.so")
 
 TRACE_ITERS = 64
 
@@ -39,13 +40,15 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("frontier_tau", ctypes.c_float),
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("blocked", ctypes.c_int32), ("block_shift", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("binned", ctypes.c_int32), ("bin_shift", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("dense_iterations", ctypes.c_int32),
                 ("sparse_iterations", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
                 ("blocked_prepared", ctypes.c_int32), ("blocked_iterations", ctypes.c_int32),
+                ("binned_iterations", ctypes.c_int32), ("num_bins", ctypes.c_int32),
+                ("ms_bin_prepare", ctypes.c_float),
                 ("frontier_edges", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
                 ("ms_total", ctypes.c_double),
                 ("changed", ctypes.c_int64 * TRACE_ITERS), ("sparse", ctypes.c_int32 * TRACE_ITERS),
@@ -139,13 +142,17 @@ def default_opts() -> Opts:
 
 
 def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None,
-              block_shift=None) -> Opts:
-    """blocked: None/"auto" -> automatic, False -> never, True -> always."""
+              block_shift=None, binned=None, bin_shift=None) -> Opts:
+    """blocked, binned: None/"auto" -> automatic, False -> never, True -> always."""
     o = default_opts()
     if blocked is not None and blocked != "auto":
         o.blocked = 1 if blocked else 0
     if block_shift is not None:
         o.block_shift = int(block_shift)
+    if binned is not None and binned != "auto":
+        o.binned = 1 if binned else 0
+    if bin_shift is not None:
+        o.bin_shift = int(bin_shift)
     if max_iters is not None:
         o.max_iters = int(max_iters)
     if frontier_tau is not None:
@@ -183,7 +190,7 @@ def _check_vec(t, name, n=None):
 def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
            max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None, block_shift=None,
-           check=True):
+           binned=None, bin_shift=None, check=True):
     """Connected components of a symmetric int32 CSR graph resident on the GPU.
 
     Returns (labels, stats); labels[u] is the smallest vertex of u's component.
@@ -201,7 +208,7 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift)
     if workspace is None:
         wsb = workspace_bytes(n, nnz, opts)
         if wsb == 0:

@@ -1,0 +1,266 @@
+// Binned dense SpMV pass for graphs whose grandparent vector does not fit in
+// L2.  Included by fastsv.hip after kernels.h.
+//
+// The dense step needs m[u] = min_{v in N(u)} G[v] for every row u (Alg. 3,
+// the (select2nd, min) SpMV).  The plain pull pass gathers G[v] in the CSR's
+// order, which for a graph with scattered ids is random over all of G: each
+// 4-byte value costs a whole cache line from the fabric.
+//
+// Here the stored entries are regrouped once per solve.  Rows are cut into
+// bins of W = 2^S consecutive vertices.  Because the CSR is symmetric, the
+// entries (u, v) with u in bin b are exactly the entries (v, u) of the CSR
+// whose column u falls in bin b; listing those in the CSR's own storage order
+// (rows v ascending) gives bin b's entries sorted by source v.  The layout
+// stores, per entry of bin b, the source v (int32) and the row offset u - bW
+// (uint16), bin after bin.  A dense iteration then runs one workgroup per
+// bin: it streams the bin's entries, gathers G[v] in ascending order of v,
+// and min-reduces into an LDS window of W rows.  The sweep is cut into source
+// ranges, one launch each, so that all workgroups gather from the same slice
+// of G at the same time and share its lines in L2.  Rows are then finished as
+// in the pull pass (M update, aggressive and stochastic hooks).
+// The minimum is order-free, so the iterate is bit-identical to the pull
+// pass's.
+//
+// Building the layout: a count pass (entries per chunk of tiles and bin), an
+// exclusive scan of the counts in bin-major order, which gives every
+// (bin, chunk) run its first position, and a fill pass that sorts each round
+// of tiles by bin in LDS and writes the runs (the order inside a run is not
+// fixed; no result depends on it).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "engine.h"
+#include "kernels.h"
+
+namespace fsv {
+
+// Entries per (chunk, bin) in bin-major order: cnt[b * nchunks + k].  Chunk
+// k is the tiles [k * chunk_tiles, (k + 1) * chunk_tiles), i.e. the entries
+// from k * chunk_tiles * kTileEntries on.  Entries with a column id outside
+// [0, n) are not counted (and not placed by the fill pass).
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, const int *__restrict__ col,
+                                                           int shift, int nbins, int nchunks, int chunk_tiles,
+                                                           int *__restrict__ cnt) {
+    __shared__ int hist[kMaxBins];
+    const int tid = threadIdx.x;
+    const int k = xcd_major(blockIdx.x, gridDim.x);
+    for (int b = tid; b < nbins; b += kBinThreads) hist[b] = 0;
+    __syncthreads();
+    const int64_t e0 = (int64_t)k * chunk_tiles * kTileEntries;
+    const int64_t e1 = min(e0 + (int64_t)chunk_tiles * kTileEntries, nnz);
+    const bool vec = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
+    for (int64_t e = e0 + 4 * tid; e < e1; e += 4 * kBinThreads) {
+        if (vec && e + 4 <= e1) {
+            const v4i c = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + e));
+            if (c.x >= 0 && c.x < n) atomicAdd(&hist[c.x >> shift], 1);
+            if (c.y >= 0 && c.y < n) atomicAdd(&hist[c.y >> shift], 1);
+            if (c.z >= 0 && c.z < n) atomicAdd(&hist[c.z >> shift], 1);
+            if (c.w >= 0 && c.w < n) atomicAdd(&hist[c.w >> shift], 1);
+        } else {
+            for (int64_t f = e; f < min(e + 4, e1); ++f) {
+                const int c = col[f];
+                if (c >= 0 && c < n) atomicAdd(&hist[c >> shift], 1);
+            }
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < nbins; b += kBinThreads) cnt[(int64_t)b * nchunks + k] = hist[b];
+    if (k == 0 && tid == 0) cnt[(int64_t)nbins * nchunks] = 0;  // becomes the total after the scan
+}
+
+// Fill pass: one workgroup per chunk, processed kBinThreads / kWave tiles at a
+// time (one tile per wave).  Each round sorts its entries by bin in LDS and
+// writes every bin's run at the bin's cursor, which starts at the chunk's
+// offset from the scan: a (chunk, bin) run belongs to this workgroup only.
+// Dynamic LDS: 3 * nbins ints.
+__global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
+                                                          const int *__restrict__ rp, const int *__restrict__ col,
+                                                          int shift, int nbins, int nchunks, int chunk_tiles,
+                                                          const int *__restrict__ off, int *__restrict__ bsrc,
+                                                          unsigned short *__restrict__ bdst) {
+    constexpr int kWaves = kBinThreads / kWave;
+    extern __shared__ int s_dyn[];
+    int *cur = s_dyn;               // next free position of the bin's run
+    int *hist = s_dyn + nbins;      // round's count per bin
+    int *loff = s_dyn + 2 * nbins;  // round's exclusive offset per bin in the stage
+    __shared__ int win[kWaves][kRowWin];
+    __shared__ int sv[kWaves * kTileEntries];  // staged sources
+    __shared__ int su[kWaves * kTileEntries];  // staged columns
+    __shared__ int s_wsum[kWaves];
+    const int tid = threadIdx.x;
+    const int wave = tid / kWave;
+    const int lane = lane_id();
+    const int k = xcd_major(blockIdx.x, gridDim.x);
+    for (int b = tid; b < nbins; b += kBinThreads) cur[b] = off[(int64_t)b * nchunks + k];
+    const int mask = (1 << shift) - 1;
+    const int per = (nbins + kBinThreads - 1) / kBinThreads;
+    const int b0 = tid * per, b1 = min(b0 + per, nbins);
+    for (int b = b0; b < b1; ++b) hist[b] = 0;
+    for (int t0 = k * chunk_tiles; t0 < min((k + 1) * chunk_tiles, ntiles); t0 += kWaves) {
+        const int t = t0 + wave;
+        const bool tile_ok = t < min((k + 1) * chunk_tiles, ntiles);
+        const Tile T = tile_ok ? tiles[t] : Tile{0, 0, 0, -1};
+        const int a = T.e0 + lane * kPerLane;
+        const int cnt = tile_ok ? max(0, min(kPerLane, T.e1 - a)) : 0;
+        int c[kPerLane];
+        if (cnt == kPerLane && ((reinterpret_cast<uintptr_t>(col + a) & 15) == 0)) {
+            const v4i *p = reinterpret_cast<const v4i *>(col + a);
+#pragma unroll
+            for (int q = 0; q < kPerLane / 4; ++q) {
+                v4i v = __builtin_nontemporal_load(p + q);
+                c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
+            }
+        } else {
+            const int last = tile_ok ? T.e1 - 1 : 0;
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) c[j] = __builtin_nontemporal_load(col + min(a + j, last));
+        }
+        const int nwin = T.r_hi - T.r_lo + 2;
+        const bool in_lds = tile_ok && nwin <= kRowWin;
+        if (in_lds)
+            for (int j = lane; j < nwin; j += kWave) win[wave][j] = rp[T.r_lo + j];
+        __syncthreads();
+        const int *wrow = &win[wave][0];
+        auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
+        // source row of every entry and its rank inside its bin in this round
+        int row = T.r_lo, nxt = 0;
+        if (cnt > 0) {
+            int lo = T.r_lo, hi = T.r_hi;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rpw(mid) <= a) lo = mid;
+                else hi = mid - 1;
+            }
+            row = lo;
+            nxt = rpw(row + 1);
+        }
+        int r[kPerLane], rank[kPerLane];
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            if (j < cnt) {
+                const int e = a + j;
+                while (e >= nxt) { ++row; nxt = rpw(row + 1); }
+            }
+            r[j] = row;
+        }
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            const bool ok = j < cnt && c[j] >= 0 && c[j] < n;
+            rank[j] = ok ? atomicAdd(&hist[c[j] >> shift], 1) : -1;
+        }
+        __syncthreads();
+        // exclusive offsets of the round's bins in the stage
+        int local = 0;
+        for (int b = b0; b < b1; ++b) local += hist[b];
+        const int incl = wave_incl_sum(local);
+        if (lane == kWave - 1) s_wsum[wave] = incl;
+        __syncthreads();
+        int o = incl - local, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            o += w < wave ? s_wsum[w] : 0;
+            total += s_wsum[w];
+        }
+        for (int b = b0; b < b1; ++b) {
+            loff[b] = o;
+            o += hist[b];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            if (rank[j] >= 0) {
+                const int sidx = loff[c[j] >> shift] + rank[j];
+                sv[sidx] = r[j];
+                su[sidx] = c[j];
+            }
+        }
+        __syncthreads();
+        for (int sidx = tid; sidx < total; sidx += kBinThreads) {
+            const int u = su[sidx];
+            const int b = u >> shift;
+            const int pos = cur[b] + (sidx - loff[b]);
+            bsrc[pos] = sv[sidx];
+            bdst[pos] = (unsigned short)(u & mask);
+        }
+        __syncthreads();
+        for (int b = b0; b < b1; ++b) {
+            cur[b] += hist[b];
+            hist[b] = 0;
+        }
+        // the next round's first barrier orders these updates before any use
+    }
+}
+
+// Dense pass over the binned layout, source range r of nrange: one
+// workgroup per bin, the bin's W rows in LDS.  All bins are cut at the same
+// chunk boundaries, so the workgroups of one launch gather from the same
+// slice of G and share its lines in L2; the launches of one iteration run
+// the ranges in order.  Between launches a bin's partial minima are parked in
+// wbuf (W ints per bin): range 0 starts from INT_MAX, the last range finishes
+// the rows as the pull pass does (M update, aggressive and stochastic hooks).
+__global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks, int r, int nrange,
+                                                   const int *__restrict__ off, const int *__restrict__ bsrc,
+                                                   const unsigned short *__restrict__ bdst,
+                                                   int *__restrict__ wbuf, const int *__restrict__ F,
+                                                   int *__restrict__ Fn, const int *__restrict__ G,
+                                                   int *__restrict__ M) {
+    __shared__ int wmin[1 << kBinShiftMax];
+    constexpr int kSpan = kWave * kBinSpan;
+    constexpr int kWaves = 1024 / kWave;
+    const int tid = threadIdx.x;
+    const int lane = lane_id(), wave = tid / kWave;
+    const int b = blockIdx.x;
+    const int u0 = b << shift;
+    const int rows = min(1 << shift, n - u0);
+    int *park = wbuf + ((int64_t)b << shift);
+    if (r == 0) {
+        for (int i = tid; i < rows; i += 1024) wmin[i] = INT_MAX;
+    } else {
+        for (int i = tid; i < rows; i += 1024) wmin[i] = __builtin_nontemporal_load(park + i);
+    }
+    __syncthreads();
+    const int c0 = (int)((int64_t)nchunks * r / nrange), c1 = (int)((int64_t)nchunks * (r + 1) / nrange);
+    const int p1 = off[(int64_t)b * nchunks + c1];
+    for (int base = off[(int64_t)b * nchunks + c0] + wave * kSpan; base < p1; base += kWaves * kSpan) {
+        int v[kBinSpan], d[kBinSpan];
+        if (base + kSpan <= p1) {
+#pragma unroll
+            for (int x = 0; x < kBinSpan; ++x) {
+                v[x] = __builtin_nontemporal_load(bsrc + base + x * kWave + lane);
+                d[x] = __builtin_nontemporal_load(bdst + base + x * kWave + lane);
+            }
+#pragma unroll
+            for (int x = 0; x < kBinSpan; ++x) v[x] = G[v[x]];
+#pragma unroll
+            for (int x = 0; x < kBinSpan; ++x) atomicMin(&wmin[d[x]], v[x]);
+        } else {
+#pragma unroll
+            for (int x = 0; x < kBinSpan; ++x) {
+                const int p = min(base + x * kWave + lane, p1 - 1);
+                v[x] = __builtin_nontemporal_load(bsrc + p);
+                d[x] = __builtin_nontemporal_load(bdst + p);
+            }
+#pragma unroll
+            for (int x = 0; x < kBinSpan; ++x) v[x] = G[v[x]];
+#pragma unroll
+            for (int x = 0; x < kBinSpan; ++x)
+                if (base + x * kWave + lane < p1) atomicMin(&wmin[d[x]], v[x]);
+        }
+    }
+    __syncthreads();
+    if (r + 1 < nrange) {
+        for (int i = tid; i < rows; i += 1024) __builtin_nontemporal_store(wmin[i], park + i);
+        return;
+    }
+    for (int i = tid; i < rows; i += 1024) {
+        const int m = wmin[i];
+        if (m == INT_MAX) continue;
+        finish_row<false>(u0 + i, m, false, F, Fn, G, M);
+    }
+}
+
+}  // namespace fsv

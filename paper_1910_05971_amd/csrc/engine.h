@@ -27,6 +27,7 @@ constexpr int kPushThreads = 256;
 constexpr int kPushSlots = 2048;              // edge slots per workgroup
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 struct Tile {
     int e0, e1;      // entry range [e0, e1)
@@ -49,6 +50,28 @@ struct Counters {
 };
 
 constexpr int kMaxBlocks = 64;
+
+// ---- binned dense pass geometry ----
+constexpr int kMaxBins = 2048;          // bins per graph (scatter histogram in LDS)
+constexpr int kBinShiftMax = 15;        // 2^15 rows = 128 KB LDS window in the apply pass
+constexpr int kBinShiftMin = 8;
+constexpr int kBinSpan = 16;            // entries per lane and step of the binned dense pass
+constexpr int kBinRangeRowsLog = 6;    // source range of one binned launch: 2^(shift + 6) rows (8 MB of G at shift 15)
+constexpr int kBinThreads = 256;        // layout build: one tile per wave and round
+constexpr int64_t kBinMaxCounts = 1 << 27;  // (bin, chunk) counters of the layout build
+constexpr int kBinChunkTilesMin = 32;   // tiles per chunk of the layout build (8 rounds of 4)
+constexpr int kNumXcd = 8;              // workgroups are dealt round-robin to the XCDs
+
+// Workgroup index -> work index such that the workgroups on one XCD (index
+// congruent mod kNumXcd) take consecutive work items: their writes to
+// neighbouring runs meet in one L2.
+__host__ __device__ inline int xcd_major(int bid, int nblocks) {
+    const int per = nblocks / kNumXcd, rem = nblocks % kNumXcd;
+    const int x = bid % kNumXcd, i = bid / kNumXcd;
+    // XCD x gets per (+1 for the first rem XCDs) consecutive items
+    return x * per + (x < rem ? x : rem) + i;
+}
+constexpr int kBinAutoMinN = 1 << 22;   // automatic mode: graphs with more vertices (G well beyond L2)
 
 // A graph entering or leaving the serving pool (see server.hip).
 struct SrvNew {

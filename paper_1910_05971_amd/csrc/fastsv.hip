@@ -41,6 +41,7 @@
 #include "fastsv.h"
 #include "engine.h"
 #include "kernels.h"
+#include "binned.h"
 
 namespace fsv {
 
@@ -59,13 +60,42 @@ struct Layout {
     bool cb;         // column-blocked arrays present
     int cb_shift, nblk;
     int64_t scan_len, scan_sums;
+    bool bin;        // binned dense pass arrays present
+    int bin_shift, nbins, bin_ranges, nchunks, chunk_tiles;
+    int64_t bin_scan_len;
     size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_tiles, off_ctr;
     size_t off_cbcol, off_segptr, off_segrow, off_cnte, off_cnts, off_sums_e, off_sums_s, off_cbtiles, off_info;
+    size_t off_bsrc, off_bdst, off_bcnt, off_bsums, off_wbuf;
     size_t total;
 };
 
-// cb_mode: -1 automatic, 0 off, 1 forced; shift 0 = automatic block width.
-Layout layout_for(int64_t n, int64_t nnz, int cb_mode = -1, int shift = 0) {
+// Dense-pass choices that change the workspace layout.
+struct LayoutOpts {
+    int cb_mode = -1;    // column-blocked: -1 automatic, 0 off, 1 forced
+    int cb_shift = 0;    // 0 = automatic block width
+    int bin_mode = -1;   // binned: -1 automatic, 0 off, 1 forced
+    int bin_shift = 0;   // 0 = automatic bin width
+};
+
+// the batch entry point uses the plain passes (column ids are graph-local)
+LayoutOpts batch_layout_opts() {
+    LayoutOpts lo;
+    lo.cb_mode = 0;
+    lo.bin_mode = 0;
+    return lo;
+}
+
+LayoutOpts layout_opts(const fastsv_opts &o) {
+    LayoutOpts lo;
+    lo.cb_mode = o.blocked;
+    lo.cb_shift = o.block_shift;
+    lo.bin_mode = o.binned;
+    lo.bin_shift = o.bin_shift;
+    return lo;
+}
+
+Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
+    const int cb_mode = lo.cb_mode, shift = lo.cb_shift;
     Layout L{};
     L.n = n;
     L.nnz = nnz;
@@ -100,6 +130,34 @@ Layout layout_for(int64_t n, int64_t nnz, int cb_mode = -1, int shift = 0) {
         L.off_cbtiles = take(sizeof(Tile) * (size_t)(L.ntiles + kMaxBlocks));
         L.off_info = take(sizeof(CbInfo));
     }
+    // binned dense passes: per stored entry its source (int32) and row offset
+    // in the bin (uint16), the (bin, chunk) counts and their scan, the slice
+    // table of the dense pass
+    const int bsh = lo.bin_shift > 0 ? lo.bin_shift : kBinShiftMax;
+    const int64_t nb = (n + (int64_t(1) << bsh) - 1) >> bsh;
+    L.bin = nnz > 0 && nb <= kMaxBins && (lo.bin_mode == 1 || (lo.bin_mode == -1 && n > kBinAutoMinN));
+    if (L.bin) {
+        L.bin_shift = bsh;
+        L.nbins = (int)nb;
+        // chunks of whole rounds of tiles: at least kBinChunkTilesMin tiles, so that a
+        // (chunk, bin) run spans whole cache lines, and few enough for the counter budget
+        const int64_t rounds = (L.ntiles + kBinThreads / kWave - 1) / (kBinThreads / kWave);
+        int64_t ct = (kBinThreads / kWave) * ((nb * rounds + kBinMaxCounts - 1) / kBinMaxCounts);
+        if (ct < kBinChunkTilesMin) ct = kBinChunkTilesMin;
+        L.chunk_tiles = (int)ct;
+        L.nchunks = (int)((L.ntiles + ct - 1) / ct);
+        L.bin_scan_len = nb * L.nchunks + 1;
+        // source ranges of the dense pass (one launch each): 2^(bsh + kBinRangeRowsLog) rows
+        const int rl = bsh + kBinRangeRowsLog;
+        int64_t nr = (n + ((int64_t)1 << rl) - 1) >> rl;
+        if (nr > L.nchunks) nr = L.nchunks;
+        L.bin_ranges = (int)nr;
+        L.off_bsrc = take(sizeof(int) * (size_t)nnz);
+        L.off_bdst = take(sizeof(unsigned short) * (size_t)nnz);
+        L.off_bcnt = take(sizeof(int) * (size_t)L.bin_scan_len);
+        L.off_bsums = take(sizeof(int) * (size_t)(grid_for(L.bin_scan_len, kScanBlock) + 1));
+        L.off_wbuf = nr > 1 ? take(sizeof(int) * (size_t)(nb << bsh)) : 0;
+    }
     L.total = p;
     return L;
 }
@@ -114,6 +172,10 @@ struct Workspace {
     int *cb_col, *seg_ptr, *seg_row, *cnt_e, *cnt_s, *sums_e, *sums_s;
     Tile *cb_tiles;
     CbInfo *info;
+    int *bsrc;
+    unsigned short *bdst;
+    int *bcnt, *bsums;
+    int *wbuf;
 };
 
 Workspace carve(void *base, const Layout &L) {
@@ -136,6 +198,13 @@ Workspace carve(void *base, const Layout &L) {
         w.sums_s = reinterpret_cast<int *>(p + L.off_sums_s);
         w.cb_tiles = reinterpret_cast<Tile *>(p + L.off_cbtiles);
         w.info = reinterpret_cast<CbInfo *>(p + L.off_info);
+    }
+    if (L.bin) {
+        w.bsrc = reinterpret_cast<int *>(p + L.off_bsrc);
+        w.bdst = reinterpret_cast<unsigned short *>(p + L.off_bdst);
+        w.bcnt = reinterpret_cast<int *>(p + L.off_bcnt);
+        w.bsums = reinterpret_cast<int *>(p + L.off_bsums);
+        w.wbuf = L.bin_ranges > 1 ? reinterpret_cast<int *>(p + L.off_wbuf) : nullptr;
     }
     return w;
 }
@@ -170,6 +239,16 @@ void cb_prepare(const Layout &L, const Workspace &w, const int *rp, const int *c
     hipLaunchKernelGGL(k_cb_sentinels, dim3(1), dim3(kMaxBlocks), 0, stream, L.nblk, w.info, w.seg_ptr);
     hipLaunchKernelGGL(k_cb_tiles, dim3(grid_for(L.nnz, 256)), dim3(256), 0, stream, L.nblk, w.info, w.seg_ptr,
                        w.cb_tiles);
+}
+
+// Build the binned layout (count, scan, fill, slice table).
+void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream) {
+    hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, L.bin_shift,
+                       L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
+    scan_inplace(w.bcnt, L.bin_scan_len, w.bsums, stream);
+    hipLaunchKernelGGL(k_bin_fill, dim3(L.nchunks), dim3(kBinThreads), 3 * sizeof(int) * (size_t)L.nbins, stream,
+                       w.tiles, (int)L.ntiles, n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt,
+                       w.bsrc, w.bdst);
 }
 
 // ---- launch wrappers ----
@@ -318,6 +397,8 @@ bool opts_ok(const fastsv_opts &o, int64_t n) {
     if (o.block_shift != 0 && (o.block_shift < 4 || o.block_shift > 30)) return false;
     if (o.block_shift != 0 && n > 0 && ((n + (int64_t(1) << o.block_shift) - 1) >> o.block_shift) > kMaxBlocks)
         return false;
+    if (o.binned < -1 || o.binned > 1) return false;
+    if (o.bin_shift != 0 && (o.bin_shift < kBinShiftMin || o.bin_shift > kBinShiftMax)) return false;
     return true;
 }
 
@@ -374,6 +455,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
     // iteration 1 reads F = iota from F[0] and writes Fn = F[1]
     launch_init(stream, n, w.F[0], w.F[1], P.G, w.M, 0);
     launch_build_tiles(stream, n, 0, 0, (int)nnz, P.rp, w.tiles);
+    // binned layout: built before the first dense iteration that gathers
+    int bin_state = (L.bin && !base && !L.cb) ? 0 : -1;  // 0 not built, 1 ready, -1 unused
     HIP_TRY(hipGetLastError());
 
     int *G = P.G;
@@ -406,6 +489,20 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             cb_state = (cbh.flags & 1) ? -1 : 1;  // rows not sorted: keep the plain pass
             if (stats) stats->blocked_prepared = 1;
         }
+        if (!sparse && it > 1 && bin_state == 0) {
+            if (opts.timing) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
+            bin_prepare(L, w, n, P.rp, P.col, stream);
+            HIP_TRY(hipGetLastError());
+            if (opts.timing) {
+                HIP_TRY(hipEventRecord(ctx->ev[1], stream));
+                HIP_TRY(hipEventSynchronize(ctx->ev[1]));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+                if (stats) stats->ms_bin_prepare = ms;
+            }
+            bin_state = 1;
+            if (stats) stats->num_bins = L.nbins;
+        }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
         if (sparse) {
             launch_sparse(stream, w.frontier, w.eoff, (int)prev_fcnt, (int)prev_edges, P.rp, P.col, P.vbase, F, Fn, G,
@@ -427,6 +524,11 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 }
                 hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
                 if (stats) stats->blocked_iterations++;
+            } else if (bin_state == 1) {
+                for (int r = 0; r < L.bin_ranges; ++r)
+                    hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bin_shift, L.nchunks, r,
+                                       L.bin_ranges, w.bcnt, w.bsrc, w.bdst, w.wbuf, F, Fn, G, w.M);
+                if (stats) stats->binned_iterations++;
             } else {
                 launch_dense(stream, base ? kDenseBaseGather : kDenseGather, w.tiles, (int)ntiles, P.rp, P.col,
                              P.vbase, F, Fn, G, w.M);
@@ -531,6 +633,8 @@ fastsv_opts fastsv_default_opts(void) {
     o.timing = 0;
     o.blocked = -1;
     o.block_shift = 0;
+    o.binned = -1;
+    o.bin_shift = 0;
     return o;
 }
 
@@ -587,7 +691,7 @@ size_t fastsv_workspace_bytes_opts(int32_t n, int64_t nnz, const fastsv_opts *op
     if (n < 0 || nnz < 0 || nnz > INT_MAX - kTileEntries) return 0;
     fastsv_opts o = opts ? *opts : fastsv_default_opts();
     if (!opts_ok(o, n)) return 0;
-    return layout_for(n, nnz, o.blocked, o.block_shift).total;
+    return layout_for(n, nnz, layout_opts(o)).total;
 }
 
 int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
@@ -602,7 +706,7 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, co
     if (stats) memset(stats, 0, sizeof(*stats));
     if (n == 0) return FASTSV_OK;
     if (!rp || !labels || (nnz > 0 && !col)) return FASTSV_EINVAL;
-    const Layout L = layout_for(n, nnz, opts.blocked, opts.block_shift);
+    const Layout L = layout_for(n, nnz, layout_opts(opts));
     HIP_TRY(hipSetDevice(ctx->device));
     int st = get_workspace(ctx, d_ws, ws_bytes, L.total);
     if (st != FASTSV_OK) return st;
@@ -648,7 +752,7 @@ int fastsv_cc_edges(fastsv_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     if (n == 0) return FASTSV_OK;
     if (!labels || (m > 0 && (!src || !dst))) return FASTSV_EINVAL;
     const int64_t nnz = 2 * m;
-    const Layout L = layout_for(n, nnz, 0, 0);
+    const Layout L = layout_for(n, nnz, layout_opts(opts));
     const ExtraLayout X = edge_extra(L.total, n, m);
     HIP_TRY(hipSetDevice(ctx->device));
     int st = get_workspace(ctx, d_ws, ws_bytes, X.total);
@@ -690,7 +794,7 @@ int fastsv_cc_edges(fastsv_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
 
 size_t fastsv_batch_workspace_bytes(int32_t total_n, int64_t total_nnz) {
     if (total_n < 0 || total_nnz < 0 || total_nnz > INT_MAX - kTileEntries) return 0;
-    const Layout L = layout_for(total_n, total_nnz, 0, 0);
+    const Layout L = layout_for(total_n, total_nnz, batch_layout_opts());
     return batch_extra(L.total, total_n).total;
 }
 
@@ -710,7 +814,7 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
     if (num_graphs == 0) return total_n == 0 && total_nnz == 0 ? FASTSV_OK : FASTSV_EINVAL;
     if (!vtx_off || !edge_off || !rp || !iters || (total_n > 0 && !labels) || (total_nnz > 0 && !col))
         return FASTSV_EINVAL;
-    const Layout L = layout_for(total_n, total_nnz, 0, 0);
+    const Layout L = layout_for(total_n, total_nnz, batch_layout_opts());
     const ExtraLayout X = batch_extra(L.total, total_n);
     HIP_TRY(hipSetDevice(ctx->device));
     int st = get_workspace(ctx, d_ws, ws_bytes, X.total);

@@ -200,13 +200,22 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
             c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
         }
     } else {
+        // partial lane: addresses are clamped into the tile (or to entry 0 for
+        // a wave past the last tile) so that no load sits under a branch
+        const int last = tile_ok ? T.e1 - 1 : 0;
 #pragma unroll
-        for (int j = 0; j < kPerLane; ++j) c[j] = j < cnt ? __builtin_nontemporal_load(col + a + j) : 0;
+        for (int j = 0; j < kPerLane; ++j) c[j] = __builtin_nontemporal_load(col + min(a + j, last));
     }
+    // Gathers are issued unconditionally (index 0 for the lane's unused
+    // slots) and masked afterwards: a gather under a per-slot branch makes the
+    // compiler wait for every earlier load before issuing it.
     int g[kPerLane];
     if (!kBase) {
 #pragma unroll
-        for (int j = 0; j < kPerLane; ++j) g[j] = j < cnt ? (kNoGather ? c[j] : G[c[j]]) : INT_MAX;
+        for (int j = 0; j < kPerLane; ++j) {
+            const int v = kNoGather ? c[j] : G[j < cnt ? c[j] : 0];
+            g[j] = j < cnt ? v : INT_MAX;
+        }
     }
 
     const int nwin = T.r_hi - T.r_lo + 2;
@@ -235,18 +244,20 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     if (kBase) {
         // batched graphs: local column ids, shifted by the base of the row's graph
         int r = row0, nx = nxt, b = cnt > 0 ? aux[row0] : 0;
+        int gi[kPerLane];
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
-            if (j < cnt) {
-                int e = a + j;
-                if (e >= nx) {
-                    do { ++r; nx = rpw(r + 1); } while (e >= nx);
-                    b = aux[r];
-                }
-                g[j] = kNoGather ? c[j] + b : G[c[j] + b];
-            } else {
-                g[j] = INT_MAX;
+            const int e = a + j;
+            if (j < cnt && e >= nx) {
+                do { ++r; nx = rpw(r + 1); } while (e >= nx);
+                b = aux[r];
             }
+            gi[j] = j < cnt ? c[j] + b : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kPerLane; ++j) {
+            const int v = kNoGather ? gi[j] : G[gi[j]];
+            g[j] = j < cnt ? v : INT_MAX;
         }
     }
 

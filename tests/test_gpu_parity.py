@@ -181,6 +181,45 @@ def test_blocked_unsorted_rows_fall_back(gpu_ok):
     assert st.blocked_prepared == 1 and st.blocked_iterations == 0
 
 
+def test_binned_passes_trajectories(gpu_ok):
+    # binned dense passes forced on moderate graphs with narrow bins: many bins,
+    # and 1, 2 or 4 source ranges (one launch each, 2^(shift + 6) rows)
+    graphs = [(gg.rmat(14, 16, seed=61), 8), (gg.er(30000, 120000, seed=62), 8),
+              (gg.grid(120, 150, 0.6, seed=63), 8), (gg.rmat(16, 8, seed=64), 8), (gg.er(40000, 90000, seed=65), 10)]
+    for g, shift in graphs:
+        ref = check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift)
+        rp, col = to_dev(g)
+        _, st = solve(rp, col, frontier_tau=0.0, binned=True, bin_shift=shift)
+        assert st.num_bins == (g.n + (1 << shift) - 1) >> shift
+        assert st.binned_iterations == max(0, ref.iterations - 1), (g.name, st.binned_iterations)
+
+
+def test_binned_hub_and_unsorted_rows(gpu_ok):
+    # a star centre with an entry in every bin, plus rows in random order
+    n = 6000
+    pairs = [(17, v) for v in range(n) if v != 17] + [(v, v + 1) for v in range(3000, 3100)]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    rng = np.random.default_rng(9)
+    col_h = col_h.copy()
+    for u in range(n):
+        a, b = rp_h[u], rp_h[u + 1]
+        col_h[a:b] = rng.permutation(col_h[a:b])
+    g = gg.Graph("star_unsorted", n, rp_h, col_h, len(pairs))
+    check_graph(g, taus=(0.0, 1.0), trajectory=True, binned=True, bin_shift=8)
+
+
+def test_binned_too_many_bins_falls_back(gpu_ok):
+    # 2049 bins of 2^8 vertices: more than the scatter pass supports, so the pull pass runs
+    n = 2048 * 256 + 1
+    pairs = [(0, n - 1), (5, 600000 % n), (300000, 300001)]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    g = gg.Graph("many_bins", n, rp_h, col_h, len(pairs))
+    check_graph(g, taus=(0.0,), binned=True, bin_shift=8)
+    rp, col = to_dev(g)
+    _, st = solve(rp, col, frontier_tau=0.0, binned=True, bin_shift=8)
+    assert st.num_bins == 0 and st.binned_iterations == 0
+
+
 def test_validation_rejects_bad_graph(gpu_ok):
     import paper_1910_05971_amd as fs
     rp = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
@@ -222,9 +261,10 @@ def test_config_c2_rmat(gpu_ok):
     _say(f"[gpu] C2 n={g.n} nnz={g.nnz}")
     rp, col = to_dev(g)
     want = O.uf_labels(g.n, g.row_ptr, g.col)
-    for tau, blocked in ((0.0, False), (0.05, None), (0.05, True)):
-        got, st = solve(rp, col, frontier_tau=tau, blocked=blocked)
-        assert np.array_equal(got, want), f"C2 tau={tau} blocked={blocked}"
-        _say(f"[gpu] C2 tau={tau} blocked={blocked} iterations={st.iterations} changed={st.changed_list()} "
-             f"blocked_iterations={st.blocked_iterations}")
+    for tau, blocked, binned in ((0.0, False, False), (0.05, None, None), (0.05, True, False), (0.0, False, True)):
+        got, st = solve(rp, col, frontier_tau=tau, blocked=blocked, binned=binned)
+        assert np.array_equal(got, want), f"C2 tau={tau} blocked={blocked} binned={binned}"
+        _say(f"[gpu] C2 tau={tau} blocked={blocked} binned={binned} iterations={st.iterations} "
+             f"changed={st.changed_list()} blocked_iterations={st.blocked_iterations} "
+             f"binned_iterations={st.binned_iterations}")
     O.check_final(got, g.row_ptr, g.col)
