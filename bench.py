@@ -7,9 +7,12 @@ undirected edge draws, a=.57 b=c=.19 d=.05, ids permuted; seed 2), already
 resident in HBM; value = undirected edges per second.
 
 Also in the same JSON line:
-  roofline      the dense gather pass (the dominant kernel): algorithmic bytes
-                per launch / its average launch time from HIP events on the
-                call's stream, against 8 TB/s
+  roofline      the dense SpMV step (the dominant kernel: on this graph the
+                binned pass, k_bin_pull, one launch per source range):
+                algorithmic bytes of one dense iteration / its average time
+                from HIP events on the call's stream, against 8 TB/s; traffic
+                = counter-measured HBM bytes of one step (profiles/), null when
+                the kernel source has changed since they were taken
   cpu_baseline  the union-find oracle on the host, one core, the whole graph
   batched       4096 Erdos-Renyi graphs in one batched call vs one call per
                 graph (graphs/s)
@@ -50,8 +53,35 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="counter-measured HBM bytes per launch of the dense gather pass")
+                    help="counter-measured HBM bytes per dense step (see profiles/)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device three times (counter calibration) and exit")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_1910_05971_amd/csrc/kernels.h", "paper_1910_05971_amd/csrc/binned.h",
+                  "paper_1910_05971_amd/csrc/engine.h")
+
+
+def kernel_source_hash():
+    """sha256 over the device-kernel sources: counter figures taken for another
+    version of the kernels are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def copy_calibration(torch):
+    a = torch.ones(256 * 1024 * 1024, dtype=torch.int32, device="cuda")  # 1 GiB
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
 
 
 def make_graph(name):
@@ -82,14 +112,17 @@ def bench_solve(args, fs, torch, np):
         fs.cc_csr(rp, col, labels=labels, workspace=ws, **kw)
     torch.cuda.synchronize()
     log("timed region")
-    # every kernel is timed with HIP events on the call's stream
-    gather_ms, gather_n, first_ms, sparse_ms, gp_ms = 0.0, 0, 0.0, 0.0, 0.0
+    # every step of the solve is timed with HIP events on the call's stream
+    gather_ms, gather_n, first_ms, sparse_ms, gp_ms, prep_ms = 0.0, 0, 0.0, 0.0, 0.0, 0.0
     iters = []
+    binned = False
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         _, st = fs.cc_csr(rp, col, labels=labels, workspace=ws, timing=True, **kw)
         iters.append(st.iterations)
+        binned = st.binned_iterations > 0
+        prep_ms += st.ms_bin_prepare
         for k in range(min(st.iterations, 64)):
             if st.sparse[k]:
                 sparse_ms += st.ms_hook[k]
@@ -102,27 +135,37 @@ def bench_solve(args, fs, torch, np):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     n, nnz = g.n, g.nnz
-    # dense gather pass: row_ptr, col, G[col] gathers, then G, F, M per row
+    # one dense SpMV step: row_ptr, col, the G[col] gathers, then G, F, M per row
     bytes_dense = 4 * (n + 1) + 8 * nnz + 12 * n
     avg_ms = gather_ms / max(gather_n, 1)
     achieved = bytes_dense / (avg_ms * 1e-3) / 1e9 if gather_n else 0.0
-    traffic = None
+    kernel = "k_bin_pull" if binned else "k_tile_reduce<kGather>"
+    src_hash = kernel_source_hash()
+    traffic, traffic_note = None, "no counter record"
     if os.path.exists(args.traffic_json):
         try:
-            traffic = json.load(open(args.traffic_json)).get(cfg["workload"], {}).get("hook_dense_gather_bytes")
-        except Exception:
-            traffic = None
+            rec = json.load(open(args.traffic_json)).get(cfg["workload"], {})
+            if rec.get("kernel") != kernel:
+                traffic_note = f"counter record is for {rec.get('kernel')}"
+            elif rec.get("kernel_source_sha256_16") != src_hash:
+                traffic_note = "kernel source changed since the counters were taken"
+            else:
+                traffic, traffic_note = rec.get("dense_step_hbm_bytes"), rec.get("source")
+        except Exception as e:  # a malformed record reads as missing
+            traffic_note = f"unreadable counter record: {e}"
     res = {
         "value": g.m_eff * args.steps / elapsed,
         "ms_per_step": 1000.0 * elapsed / args.steps,
         "config": dict(cfg, m_eff=g.m_eff, nnz=g.nnz, iterations=iters[-1] if iters else None,
                        frontier_tau=args.tau),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_tile_reduce<kGather> (dense gather pass)", "alg_bytes_per_launch": bytes_dense,
-                     "avg_launch_ms": avg_ms, "launches": gather_n},
-        "breakdown_ms_per_step": {"first_iteration": first_ms / args.steps, "dense_gather": gather_ms / args.steps,
-                                  "sparse_push": sparse_ms / args.steps, "grandparent": gp_ms / args.steps},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
+                     "kernel": kernel, "unit_of_work": "one dense SpMV step (all launches of one iteration)",
+                     "alg_bytes_per_step": bytes_dense, "avg_step_ms": avg_ms, "steps_timed": gather_n,
+                     "kernel_source_sha256_16": src_hash},
+        "breakdown_ms_per_solve": {"first_iteration": first_ms / args.steps, "bin_layout": prep_ms / args.steps,
+                                   "dense_steps": gather_ms / args.steps, "sparse_push": sparse_ms / args.steps,
+                                   "grandparent": gp_ms / args.steps},
     }
     cpu = None
     check = None
@@ -230,6 +273,9 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import paper_1910_05971_amd as fs
 
     res = bench_solve(args, fs, torch, np)
@@ -248,7 +294,7 @@ def main():
         "data": "synthetic",
         "config": res["config"],
         "roofline": res["roofline"],
-        "breakdown_ms_per_step": res["breakdown_ms_per_step"],
+        "breakdown_ms_per_solve": res["breakdown_ms_per_solve"],
         "labels_match_oracle": res["labels_match_oracle"],
     }
     if res["cpu_baseline"]:
