@@ -76,13 +76,20 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
 // time (one tile per wave).  Each round sorts its entries by bin in LDS and
 // writes every bin's run at the bin's cursor, which starts at the chunk's
 // offset from the scan: a (chunk, bin) run belongs to this workgroup only.
+// With kFirst the pass also performs the first iteration of the method, whose
+// grandparent vector is the identity: m[u] = min N(u) (the column ids
+// themselves), and where m[u] < u, M[u] = Fn[u] = m[u] (both hooks target u,
+// since f is the identity too); it replaces the first pull pass.
 // Dynamic LDS: 3 * nbins ints.
+template <bool kFirst>
 __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
                                                           const int *__restrict__ rp, const int *__restrict__ col,
                                                           int shift, int nbins, int nchunks, int chunk_tiles,
                                                           const int *__restrict__ off, int *__restrict__ bsrc,
-                                                          unsigned short *__restrict__ bdst) {
+                                                          unsigned short *__restrict__ bdst, int *__restrict__ M,
+                                                          int *__restrict__ Fn) {
     constexpr int kWaves = kBinThreads / kWave;
+    static_assert(kWaves * kRowWin <= kWaves * kTileEntries, "row minima share the staging array");
     extern __shared__ int s_dyn[];
     int *cur = s_dyn;               // next free position of the bin's run
     int *hist = s_dyn + nbins;      // round's count per bin
@@ -91,6 +98,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict
     __shared__ int sv[kWaves * kTileEntries];  // staged sources
     __shared__ int su[kWaves * kTileEntries];  // staged columns
     __shared__ int s_wsum[kWaves];
+    // first iteration: per-row minima of the wave's tile; they live from the
+    // round's first barrier to its second, the staged sources from its fourth
+    // to its sixth, so they share memory
+    int *rminw = sv + (threadIdx.x / kWave) * kRowWin;
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = lane_id();
@@ -122,7 +133,10 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict
         const int nwin = T.r_hi - T.r_lo + 2;
         const bool in_lds = tile_ok && nwin <= kRowWin;
         if (in_lds)
-            for (int j = lane; j < nwin; j += kWave) win[wave][j] = rp[T.r_lo + j];
+            for (int j = lane; j < nwin; j += kWave) {
+                win[wave][j] = rp[T.r_lo + j];
+                if (kFirst) rminw[j] = INT_MAX;
+            }
         __syncthreads();
         const int *wrow = &win[wave][0];
         auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
@@ -152,7 +166,38 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict
             const bool ok = j < cnt && c[j] >= 0 && c[j] < n;
             rank[j] = ok ? atomicAdd(&hist[c[j] >> shift], 1) : -1;
         }
+        if (kFirst && cnt > 0) {
+            // minimum column of every row segment of the lane: into the tile's
+            // LDS row array, or straight to M / Fn for a tile whose rows are too
+            // far apart for the window
+            int rowc = r[0], cur_min = INT_MAX;
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) {
+                if (j < cnt) {
+                    if (r[j] != rowc) {
+                        if (in_lds) atomicMin(&rminw[rowc - T.r_lo], cur_min);
+                        else finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
+                        rowc = r[j];
+                        cur_min = INT_MAX;
+                    }
+                    cur_min = min(cur_min, c[j]);
+                }
+            }
+            if (in_lds) atomicMin(&rminw[rowc - T.r_lo], cur_min);
+            else finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
+        }
         __syncthreads();
+        if (kFirst && in_lds) {
+            // rows of the tile; a row that continues in a neighbouring tile
+            // needs atomics, the others are written by this wave alone
+            const int nrows = nwin - 1;
+            for (int i = lane; i < nrows; i += kWave) {
+                const int m = rminw[i];
+                if (m == INT_MAX) continue;
+                const bool shared_row = (i == 0 && wrow[0] < T.e0) || (i == nrows - 1 && wrow[nrows] > T.e1);
+                finish_row<true>(T.r_lo + i, m, shared_row, nullptr, Fn, nullptr, M);
+            }
+        }
         // exclusive offsets of the round's bins in the stage
         int local = 0;
         for (int b = b0; b < b1; ++b) local += hist[b];

@@ -241,14 +241,22 @@ void cb_prepare(const Layout &L, const Workspace &w, const int *rp, const int *c
                        w.cb_tiles);
 }
 
-// Build the binned layout (count, scan, fill, slice table).
-void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream) {
+// Build the binned layout (count, scan, fill).  With M and Fn given, the fill
+// also performs the first iteration's hooking (the grandparent vector is then
+// still the identity).
+void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream,
+                 int *M = nullptr, int *Fn = nullptr) {
     hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, L.bin_shift,
                        L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
     scan_inplace(w.bcnt, L.bin_scan_len, w.bsums, stream);
-    hipLaunchKernelGGL(k_bin_fill, dim3(L.nchunks), dim3(kBinThreads), 3 * sizeof(int) * (size_t)L.nbins, stream,
-                       w.tiles, (int)L.ntiles, n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt,
-                       w.bsrc, w.bdst);
+    const size_t lds = 3 * sizeof(int) * (size_t)L.nbins;
+    if (M)
+        hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kBinThreads), lds, stream, w.tiles, (int)L.ntiles,
+                           n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst, M, Fn);
+    else
+        hipLaunchKernelGGL(k_bin_fill<false>, dim3(L.nchunks), dim3(kBinThreads), lds, stream, w.tiles, (int)L.ntiles,
+                           n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst,
+                           nullptr, nullptr);
 }
 
 // ---- launch wrappers ----
@@ -457,6 +465,9 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
     launch_build_tiles(stream, n, 0, 0, (int)nnz, P.rp, w.tiles);
     // binned layout: built before the first dense iteration that gathers
     int bin_state = (L.bin && !base && !L.cb) ? 0 : -1;  // 0 not built, 1 ready, -1 unused
+    // when later iterations will run dense, the layout build also performs the
+    // first iteration (it streams the same column ids)
+    const bool fuse_first = bin_state == 0 && opts.frontier_tau < 1.0f;
     HIP_TRY(hipGetLastError());
 
     int *G = P.G;
@@ -510,7 +521,14 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             // frontier ids, offsets, row starts and values; per slot col and an M read-modify-write
             alg += 16 * prev_fcnt + 12 * prev_edges;
         } else {
-            if (it == 1) {
+            if (it == 1 && fuse_first) {
+                bin_prepare(L, w, n, P.rp, P.col, stream, w.M, Fn);
+                bin_state = 1;
+                if (stats) {
+                    stats->num_bins = L.nbins;
+                    stats->bin_fused_first = 1;
+                }
+            } else if (it == 1) {
                 launch_dense(stream, base ? kDenseBaseIota : kDenseIota, w.tiles, (int)ntiles, P.rp, P.col, P.vbase,
                              F, Fn, G, w.M);
             } else if (cb_state == 1) {

@@ -35,6 +35,17 @@ __device__ __forceinline__ int wave_incl_sum(int v) {
     return v;
 }
 
+// Aggressive hook Fn[u] <-min m and stochastic hook Fn[F[u]] <-min m of a
+// row whose minimum m is below G[u].  Fn only decreases while hooks run, so a
+// read that already shows a value <= m (possibly an older one) proves the
+// atomic would change nothing: hot targets (shared roots) then cost a load
+// instead of an atomic.
+__device__ __forceinline__ void hook_row(int u, int m, const int *__restrict__ F, int *__restrict__ Fn) {
+    if (Fn[u] > m) atomicMin(Fn + u, m);
+    const int x = F[u];
+    if (x != u && Fn[x] > m) atomicMin(Fn + x, m);
+}
+
 // Apply the result m of row u: M update, then the two hooks if they can
 // change anything.  `shared_row` is set when other tiles also hold entries of
 // row u (its M slot then needs an atomic).
@@ -62,12 +73,7 @@ __device__ __forceinline__ void finish_row(int u, int m, bool shared_row, const 
         if (shared_row) atomicMin(M + u, m);
         else M[u] = m;
     }
-    int gu = G[u];
-    if (m < gu) {
-        atomicMin(Fn + u, m);
-        int x = F[u];
-        if (x != u) atomicMin(Fn + x, m);
-    }
+    if (m < G[u]) hook_row(u, m, F, Fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,11 +349,7 @@ __global__ void k_hook_rows(int n, const int *__restrict__ M, const int *__restr
     int stride = gridDim.x * blockDim.x;
     for (int u = i; u < n; u += stride) {
         int m = M[u];
-        if (m < G[u]) {
-            atomicMin(Fn + u, m);
-            int x = F[u];
-            if (x != u) atomicMin(Fn + x, m);
-        }
+        if (m < G[u]) hook_row(u, m, F, Fn);
     }
 }
 
@@ -848,14 +850,7 @@ __global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
             if (val == INT_MAX) continue;
             int u = col[row + (s - off)] + vb;
             int old = atomicMin(M + u, val);
-            if (val < old) {
-                int gu = G[u];
-                if (val < gu) {
-                    atomicMin(Fn + u, val);
-                    int x = F[u];
-                    if (x != u) atomicMin(Fn + x, val);
-                }
-            }
+            if (val < old && val < G[u]) hook_row(u, val, F, Fn);
         }
     }
 }
