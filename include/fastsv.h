@@ -82,6 +82,13 @@ typedef struct {
                                (the default: graphs with more than 2^22 vertices).  Same iterates
                                either way; not used when the graph needs more than 2048 bins. */
     int32_t bin_shift;      /* log2 of the bin width in vertices; 0 = automatic (15); 8..15 */
+    int32_t sv_flags;       /* convergence ablation (Sec. 5.2): which of the four changes of Sec. 3
+                               that turn Algorithm 1 into Algorithm 2 are applied.  Bit 1 grandparent
+                               hooking (Sec. 3.1), 2 stochastic hooking (3.2), 4 aggressive hooking
+                               (3.3), 8 early termination on gf (3.4).  15 (the default) is FastSV;
+                               0 is Algorithm 1; the paper's sv1..sv5 add them in this order
+                               (0, 1, 3, 7, 15).  Other than 15: dense pull passes only, no batch
+                               entry point (FASTSV_EINVAL there), the server ignores it. */
 } fastsv_opts;
 
 #define FASTSV_TRACE_ITERS 64
@@ -158,6 +165,25 @@ size_t fastsv_workspace_bytes_opts(int32_t n, int64_t nnz, const fastsv_opts *op
 int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
                   const int32_t *d_col_idx, int32_t *d_labels, void *d_ws, size_t ws_bytes,
                   hipStream_t stream, const fastsv_opts *opts, fastsv_stats *stats);
+
+/*
+ * The same from a given parent vector instead of the identity (Alg. 3 takes
+ * the parent vector f as input and duplicates it into gf): restart after
+ * edges were added, from the labels of the graph before.
+ *
+ *   d_f_init   int32[n], each f_init[u] a vertex of u's component in the graph
+ *              with 0 <= f_init[u] <= u (labels or any iterate of an earlier
+ *              solve of a subgraph qualify).  With opts.validate the bounds are
+ *              checked (FASTSV_ERANGE); membership in u's component cannot be
+ *              checked, and without it the labels are unspecified.  May alias
+ *              d_labels (in-place restart).
+ *   other arguments as fastsv_cc_csr; opts.sv_flags must be 15 (FASTSV_EINVAL).
+ * From f_init the iterates follow Alg. 3 with that input; the first iteration
+ * gathers gf like every later one.
+ */
+int fastsv_cc_csr_warm(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
+                       const int32_t *d_f_init, int32_t *d_labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                       const fastsv_opts *opts, fastsv_stats *stats);
 
 /*
  * Edge-list entry (the problem statement of Sec. 1 and the edge form of

@@ -31,7 +31,7 @@ FASTSV_ENOTCONVERGED = -6
 FASTSV_EBUSY = -7
 
 __all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "cc_edges", "cc_batch_csr", "workspace_bytes",
-           "load_library",
+           "load_library", "make_opts", "default_opts", "context", "SV_FLAGS",
            "FASTSV_OK", "FASTSV_EINVAL", "FASTSV_ERANGE", "FASTSV_EOVERFLOW", "FASTSV_ENOMEM",
            "FASTSV_EHIP", "FASTSV_ENOTCONVERGED", "FASTSV_EBUSY"]
 
@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("frontier_tau", ctypes.c_float),
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("blocked", ctypes.c_int32), ("block_shift", ctypes.c_int32),
-                ("binned", ctypes.c_int32), ("bin_shift", ctypes.c_int32)]
+                ("binned", ctypes.c_int32), ("bin_shift", ctypes.c_int32), ("sv_flags", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -102,6 +102,9 @@ def load_library():
             lib.fastsv_cc_csr.restype = ctypes.c_int
             lib.fastsv_cc_csr.argtypes = [vp, i32, i64, vp, vp, vp, vp, sz, vp,
                                           ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+            lib.fastsv_cc_csr_warm.restype = ctypes.c_int
+            lib.fastsv_cc_csr_warm.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, sz, vp,
+                                               ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
             lib.fastsv_edges_workspace_bytes.restype = sz
             lib.fastsv_edges_workspace_bytes.argtypes = [i32, i64]
             lib.fastsv_cc_edges.restype = ctypes.c_int
@@ -141,10 +144,16 @@ def default_opts() -> Opts:
     return load_library().fastsv_default_opts()
 
 
+SV_FLAGS = {"sv1": 0, "sv2": 1, "sv3": 3, "sv4": 7, "sv5": 15}
+
+
 def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None,
-              block_shift=None, binned=None, bin_shift=None) -> Opts:
-    """blocked, binned: None/"auto" -> automatic, False -> never, True -> always."""
+              block_shift=None, binned=None, bin_shift=None, sv_flags=None) -> Opts:
+    """blocked, binned: None/"auto" -> automatic, False -> never, True -> always.
+    sv_flags: 0..15 or one of SV_FLAGS' names (None: FastSV)."""
     o = default_opts()
+    if sv_flags is not None:
+        o.sv_flags = SV_FLAGS[sv_flags] if isinstance(sv_flags, str) else int(sv_flags)
     if blocked is not None and blocked != "auto":
         o.blocked = 1 if blocked else 0
     if block_shift is not None:
@@ -190,10 +199,12 @@ def _check_vec(t, name, n=None):
 def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
            max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None, block_shift=None,
-           binned=None, bin_shift=None, check=True):
+           binned=None, bin_shift=None, sv_flags=None, f_init=None, check=True):
     """Connected components of a symmetric int32 CSR graph resident on the GPU.
 
     Returns (labels, stats); labels[u] is the smallest vertex of u's component.
+    ``f_init`` (int32[n] on the device, may be ``labels`` itself) starts the
+    iteration from that parent vector (fastsv_cc_csr_warm).
     With ``check=False`` the status is returned instead of raising:
     (labels, stats, status)."""
     _check_vec(row_ptr, "row_ptr")
@@ -208,7 +219,7 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift, sv_flags)
     if workspace is None:
         wsb = workspace_bytes(n, nnz, opts)
         if wsb == 0:
@@ -220,14 +231,22 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     stats = Stats()
     lib = load_library()
-    st = lib.fastsv_cc_csr(context(dev.index if dev.index is not None else torch.cuda.current_device()),
-                           n, nnz, _ptr(row_ptr), _ptr(col), _ptr(labels),
-                           ctypes.c_void_p(aligned), ws_bytes, ctypes.c_void_p(s.cuda_stream),
-                           ctypes.byref(opts), ctypes.byref(stats))
+    ctx = context(dev.index if dev.index is not None else torch.cuda.current_device())
+    if f_init is None:
+        st = lib.fastsv_cc_csr(ctx, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(labels),
+                               ctypes.c_void_p(aligned), ws_bytes, ctypes.c_void_p(s.cuda_stream),
+                               ctypes.byref(opts), ctypes.byref(stats))
+    else:
+        _check_vec(f_init, "f_init", n)
+        if f_init.device != dev:
+            raise ValueError("f_init must be on the graph's device")
+        st = lib.fastsv_cc_csr_warm(ctx, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(f_init), _ptr(labels),
+                                    ctypes.c_void_p(aligned), ws_bytes, ctypes.c_void_p(s.cuda_stream),
+                                    ctypes.byref(opts), ctypes.byref(stats))
     if not check:
         return labels, stats, st
     if st != FASTSV_OK:
-        raise FastSVError(st, "fastsv_cc_csr")
+        raise FastSVError(st, "fastsv_cc_csr_warm" if f_init is not None else "fastsv_cc_csr")
     return labels, stats
 
 

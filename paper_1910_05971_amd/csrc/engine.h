@@ -51,6 +51,8 @@ struct Counters {
 
 constexpr int kMaxBlocks = 64;
 
+constexpr int kSvFastSV = 15;  // all four changes of Sec. 3: Algorithm 2
+
 // ---- binned dense pass geometry ----
 constexpr int kMaxBins = 2048;          // bins per graph (scatter histogram in LDS)
 constexpr int kBinShiftMax = 15;        // 2^15 rows = 128 KB LDS window in the apply pass

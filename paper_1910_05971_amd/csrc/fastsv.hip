@@ -91,6 +91,10 @@ LayoutOpts layout_opts(const fastsv_opts &o) {
     lo.cb_shift = o.block_shift;
     lo.bin_mode = o.binned;
     lo.bin_shift = o.bin_shift;
+    if (o.sv_flags != kSvFastSV) {  // ablation variants run the plain pull pass only
+        lo.cb_mode = 0;
+        lo.bin_mode = 0;
+    }
     return lo;
 }
 
@@ -277,18 +281,18 @@ void launch_dense(hipStream_t s, int mode, const Tile *tiles, int ntiles, const 
     const dim3 grid(grid_for(ntiles, kHookWaves)), block(kWave * kHookWaves);
     switch (mode) {
         case kDenseIota:
-            hipLaunchKernelGGL((k_tile_reduce<kIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M);
+            hipLaunchKernelGGL((k_tile_reduce<kIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M, 0);
             break;
         case kDenseGather:
-            hipLaunchKernelGGL((k_tile_reduce<kGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M);
+            hipLaunchKernelGGL((k_tile_reduce<kGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M, 0);
             break;
         case kDenseBaseIota:
             hipLaunchKernelGGL((k_tile_reduce<kBaseIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G,
-                               M);
+                               M, 0);
             break;
         default:
             hipLaunchKernelGGL((k_tile_reduce<kBaseGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn,
-                               G, M);
+                               G, M, 0);
             break;
     }
 }
@@ -406,6 +410,7 @@ bool opts_ok(const fastsv_opts &o, int64_t n) {
     if (o.block_shift != 0 && n > 0 && ((n + (int64_t(1) << o.block_shift) - 1) >> o.block_shift) > kMaxBlocks)
         return false;
     if (o.binned < -1 || o.binned > 1) return false;
+    if (o.sv_flags < 0 || o.sv_flags > kSvFastSV) return false;
     if (o.bin_shift != 0 && (o.bin_shift < kBinShiftMin || o.bin_shift > kBinShiftMax)) return false;
     return true;
 }
@@ -444,13 +449,89 @@ struct Problem {
     const int *vbase;  // nullable: global id of the first vertex of each row's graph
     int *lastk;        // nullable: per-vertex iteration of the last grandparent change
     int *G;            // grandparent vector, final labels in global ids
+    const int *f_init = nullptr;  // nullable: initial parent vector (Alg. 3's input f)
 };
+
+// Iteration loop of a convergence-ablation variant (opts.sv_flags other than
+// 15; Sec. 5.2 builds Algorithm 2 from Algorithm 1 by adding the four changes
+// of Sec. 3 in turn): dense pull passes only, the write buffer seeded as the
+// variant requires, Alg. 1's shortcut phase when stochastic hooking is off,
+// and the termination test on f or on gf.
+int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w, hipStream_t stream,
+                  const fastsv_opts &opts, fastsv_stats *stats, int &it, int *&fk) {
+    const int n = P.n;
+    const int64_t ntiles = L.ntiles;
+    const int fl = opts.sv_flags;
+    const bool grand = fl & 1, stoch = fl & 2, early = fl & 8;
+    if (opts.timing && !ctx->events) {
+        for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+        ctx->events = true;
+    }
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
+    launch_init(stream, n, w.F[0], w.F[1], P.G, w.M, 0);
+    launch_build_tiles(stream, n, 0, 0, (int)P.nnz, P.rp, w.tiles);
+    HIP_TRY(hipGetLastError());
+    int *G = P.G;
+    int *T = w.frontier;  // the shortcut phase's output
+    int status = FASTSV_OK;
+    it = 0;
+    const dim3 grid(grid_for(ntiles, kHookWaves)), block(kWave * kHookWaves);
+    const dim3 vgrid(grid_for(n, 256, 65536)), vblock(256);
+    for (;;) {
+        ++it;
+        int *F = w.F[(it + 1) & 1];
+        int *Fn = w.F[it & 1];
+        fk = Fn;
+        IterCounters *ic = &w.ctr->it[it & 1];
+        IterCounters *hc = &ctx->host_ctr->it[it & 1];
+        const int ti = it - 1;
+        const bool timed = opts.timing && ti < FASTSV_TRACE_ITERS;
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
+        if (ntiles > 0)
+            hipLaunchKernelGGL((k_tile_reduce<kVariant>), grid, block, 0, stream, w.tiles, (int)ntiles, P.rp, P.col,
+                               grand ? G : F, F, Fn, G, w.M, fl);
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
+        launch_zero_iter(stream, ic);
+        if (!stoch) hipLaunchKernelGGL(k_var_shortcut, vgrid, vblock, 0, stream, n, Fn, T);
+        hipLaunchKernelGGL(k_var_finish, vgrid, vblock, 0, stream, n, stoch ? Fn : T, Fn, F, G, ic, stoch ? 1 : 0,
+                           early ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
+        HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const int64_t changed = (int64_t)(hc->packed >> 32);
+        if (stats) {
+            stats->dense_iterations++;
+            if (ti < FASTSV_TRACE_ITERS) {
+                stats->changed[ti] = changed;
+                if (timed) {
+                    float a = 0, b = 0;
+                    HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+                    HIP_TRY(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+                    stats->ms_hook[ti] = a;
+                    stats->ms_gp[ti] = b;
+                }
+            }
+        }
+        if (changed == 0) break;
+        if (opts.max_iters > 0 && it >= opts.max_iters) {
+            status = FASTSV_ENOTCONVERGED;
+            break;
+        }
+    }
+    if (stats) {
+        stats->iterations = it;
+        stats->num_tiles = (int32_t)ntiles;
+    }
+    return status;
+}
 
 // The iteration loop shared by the entry points (Algorithm 3 with the
 // sparse-frontier switch).  On return `it` holds the iterations executed and
 // `fk` the buffer that holds f after the last iteration.
 int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w, hipStream_t stream,
           const fastsv_opts &opts, fastsv_stats *stats, int &it, int *&fk) {
+    if (opts.sv_flags != kSvFastSV) return solve_variant(ctx, P, L, w, stream, opts, stats, it, fk);
     const int n = P.n;
     const int64_t nnz = P.nnz;
     const int64_t ntiles = L.ntiles;
@@ -460,14 +541,21 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         ctx->events = true;
     }
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
-    // iteration 1 reads F = iota from F[0] and writes Fn = F[1]
-    launch_init(stream, n, w.F[0], w.F[1], P.G, w.M, 0);
+    // iteration 1 reads F from F[0] and writes Fn = F[1]; F = gf = mngf = Fn =
+    // iota, or all equal to the given initial parent vector (Alg. 3 duplicates
+    // its input f into gf)
+    const bool warm = P.f_init != nullptr;
+    if (warm)
+        hipLaunchKernelGGL(k_init_from, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, P.f_init, w.F[0],
+                           w.F[1], P.G, w.M);
+    else
+        launch_init(stream, n, w.F[0], w.F[1], P.G, w.M, 0);
     launch_build_tiles(stream, n, 0, 0, (int)nnz, P.rp, w.tiles);
     // binned layout: built before the first dense iteration that gathers
     int bin_state = (L.bin && !base && !L.cb) ? 0 : -1;  // 0 not built, 1 ready, -1 unused
     // when later iterations will run dense, the layout build also performs the
     // first iteration (it streams the same column ids)
-    const bool fuse_first = bin_state == 0 && opts.frontier_tau < 1.0f;
+    const bool fuse_first = bin_state == 0 && opts.frontier_tau < 1.0f && !warm;
     HIP_TRY(hipGetLastError());
 
     int *G = P.G;
@@ -492,7 +580,9 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                             (opts.frontier_tau >= 1.0f || (double)prev_edges < tau_edges);
         const int ti = it - 1;
         const bool timed = opts.timing && ti < FASTSV_TRACE_ITERS;
-        if (!sparse && it > 1 && cb_state == 0) {
+        // iteration 1 gathers too when it starts from a given f
+        const bool gathers = it > 1 || warm;
+        if (!sparse && gathers && cb_state == 0) {
             cb_prepare(L, w, P.rp, P.col, stream);
             HIP_TRY(hipGetLastError());
             HIP_TRY(hipMemcpyAsync(&cbh, w.info, sizeof(CbInfo), hipMemcpyDeviceToHost, stream));
@@ -500,7 +590,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             cb_state = (cbh.flags & 1) ? -1 : 1;  // rows not sorted: keep the plain pass
             if (stats) stats->blocked_prepared = 1;
         }
-        if (!sparse && it > 1 && bin_state == 0) {
+        if (!sparse && gathers && bin_state == 0) {
             if (opts.timing) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
             bin_prepare(L, w, n, P.rp, P.col, stream);
             HIP_TRY(hipGetLastError());
@@ -528,7 +618,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                     stats->num_bins = L.nbins;
                     stats->bin_fused_first = 1;
                 }
-            } else if (it == 1) {
+            } else if (!gathers) {
                 launch_dense(stream, base ? kDenseBaseIota : kDenseIota, w.tiles, (int)ntiles, P.rp, P.col, P.vbase,
                              F, Fn, G, w.M);
             } else if (cb_state == 1) {
@@ -538,7 +628,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                     if (nt_b <= 0) continue;
                     hipLaunchKernelGGL((k_tile_reduce<kPhase>), dim3(grid_for(nt_b, kHookWaves)), hblock, 0, stream,
                                        w.cb_tiles + cbh.tb[b], nt_b, w.seg_ptr + cbh.sbb[b] + b, w.cb_col,
-                                       w.seg_row + cbh.sbb[b], F, Fn, G, w.M);
+                                       w.seg_row + cbh.sbb[b], F, Fn, G, w.M, 0);
                 }
                 hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
                 if (stats) stats->blocked_iterations++;
@@ -552,7 +642,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                              P.vbase, F, Fn, G, w.M);
             }
             // row_ptr, col, gathers of G[col] (none while G is the identity), then G[u], F[u], M[u] per row
-            alg += 4 * ((int64_t)n + 1) + (it == 1 ? 4 : 8) * nnz + 12 * (int64_t)n + (base ? 4 * (int64_t)n : 0);
+            alg += 4 * ((int64_t)n + 1) + (gathers ? 8 : 4) * nnz + 12 * (int64_t)n + (base ? 4 * (int64_t)n : 0);
         }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
         launch_zero_iter(stream, ic);
@@ -653,6 +743,7 @@ fastsv_opts fastsv_default_opts(void) {
     o.block_shift = 0;
     o.binned = -1;
     o.bin_shift = 0;
+    o.sv_flags = kSvFastSV;
     return o;
 }
 
@@ -712,9 +803,13 @@ size_t fastsv_workspace_bytes_opts(int32_t n, int64_t nnz, const fastsv_opts *op
     return layout_for(n, nnz, layout_opts(o)).total;
 }
 
-int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
-                  int32_t *labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
-                  const fastsv_opts *opts_in, fastsv_stats *stats) {
+}  // extern "C"
+
+namespace {
+
+int cc_csr_impl(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *f_init,
+                int32_t *labels, void *d_ws, size_t ws_bytes, hipStream_t stream, const fastsv_opts *opts_in,
+                fastsv_stats *stats) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!ctx) return FASTSV_EINVAL;
     if (n < 0 || nnz < 0) return FASTSV_EINVAL;
@@ -724,6 +819,7 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, co
     if (stats) memset(stats, 0, sizeof(*stats));
     if (n == 0) return FASTSV_OK;
     if (!rp || !labels || (nnz > 0 && !col)) return FASTSV_EINVAL;
+    if (f_init && opts.sv_flags != kSvFastSV) return FASTSV_EINVAL;  // the variants start from the identity
     const Layout L = layout_for(n, nnz, layout_opts(opts));
     HIP_TRY(hipSetDevice(ctx->device));
     int st = get_workspace(ctx, d_ws, ws_bytes, L.total);
@@ -733,10 +829,14 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, co
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
         hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)n + nnz, 256, 4096)), dim3(256), 0, stream, n, (int)nnz,
                            rp, col, w.ctr);
+        if (f_init)
+            hipLaunchKernelGGL(k_validate_parents, dim3(grid_for(n, 256, 4096)), dim3(256), 0, stream, n, f_init,
+                               w.ctr);
         st = read_status(ctx, w.ctr, stream);
         if (st != FASTSV_OK) return st;
     }
     Problem P{n, nnz, rp, col, nullptr, nullptr, labels};
+    P.f_init = f_init;
     int it = 0;
     int *fk = nullptr;
     st = solve(ctx, P, L, w, stream, opts, stats, it, fk);
@@ -747,6 +847,23 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, co
     }
     if (stats) stats->ms_total = ms_since(t0);
     return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                  int32_t *labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                  const fastsv_opts *opts, fastsv_stats *stats) {
+    return cc_csr_impl(ctx, n, nnz, rp, col, nullptr, labels, d_ws, ws_bytes, stream, opts, stats);
+}
+
+int fastsv_cc_csr_warm(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                       const int32_t *f_init, int32_t *labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
+                       const fastsv_opts *opts, fastsv_stats *stats) {
+    if (!f_init) return FASTSV_EINVAL;
+    return cc_csr_impl(ctx, n, nnz, rp, col, f_init, labels, d_ws, ws_bytes, stream, opts, stats);
 }
 
 size_t fastsv_edges_workspace_bytes(int32_t n, int64_t m) {
@@ -828,6 +945,7 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
     opts.blocked = 0;  // column ids are local to each graph
     opts.block_shift = 0;
     if (!opts_ok(opts, total_n)) return FASTSV_EINVAL;
+    if (opts.sv_flags != kSvFastSV) return FASTSV_EINVAL;  // per-graph termination is FastSV's
     if (stats) memset(stats, 0, sizeof(*stats));
     if (num_graphs == 0) return total_n == 0 && total_nnz == 0 ? FASTSV_OK : FASTSV_EINVAL;
     if (!vtx_off || !edge_off || !rp || !iters || (total_n > 0 && !labels) || (total_nnz > 0 && !col))

@@ -133,6 +133,32 @@ __global__ void k_init(int n, int *__restrict__ F, int *__restrict__ Fn, int *__
     }
 }
 
+// F = Fn = G = M = f0 (a given initial parent vector; f0 may alias G).
+__global__ void k_init_from(int n, const int *__restrict__ f0, int *__restrict__ F, int *__restrict__ Fn, int *G,
+                            int *__restrict__ M) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) {
+        const int v = f0[u];
+        F[u] = v;
+        Fn[u] = v;
+        G[u] = v;
+        M[u] = v;
+    }
+}
+
+// Optional check of an initial parent vector: 0 <= f0[u] <= u.
+__global__ void k_validate_parents(int n, const int *__restrict__ f0, Counters *ctr) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int u = i; u < n; u += stride) {
+        const int v = f0[u];
+        bad |= (v < 0) || (v > u);
+    }
+    if (bad) atomicOr(&ctr->status, 1);
+}
+
 __global__ void k_zero_counters(Counters *ctr) {
     if (threadIdx.x == 0) {
         for (int i = 0; i < 2; ++i) ctr->it[i].packed = 0ull;
@@ -159,13 +185,43 @@ __global__ void k_zero_counters(Counters *ctr) {
 //               block); finish = M update of the segment's row only (the
 //               hooks run afterwards from M, see k_hook_rows)
 // ---------------------------------------------------------------------------
-enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kPhase = 4 };
+enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kPhase = 4, kVariant = 5 };
+
+// Hooking of one row in a convergence-ablation variant (the flags of
+// fastsv_opts.sv_flags): m = min over N(u) of X[v], X = gf with grandparent
+// hooking (Sec. 3.1), f without.
+//   stochastic (Sec. 3.2): one Jacobi pass whose write buffer starts as gf
+//     (the shortcut); Fn[f[u]] <-min m with no root test, plus, when
+//     aggressive (Sec. 3.3), Fn[u] <-min m.  Both are no-ops unless m < gf[u]
+//     (the write buffer starts at or below gf[u] at both targets).
+//   otherwise (Alg. 1's first phase, write buffer = copy of f): a root f[u]
+//     (f[u] = gf[u]) is hooked, Fn[f[u]] <-min m, when m < f[u]; aggressive
+//     hooking adds Fn[u] <-min m.
+__device__ __forceinline__ void finish_variant(int u, int m, int flags, const int *__restrict__ F,
+                                               int *__restrict__ Fn, const int *__restrict__ G) {
+    const bool stoch = flags & 2, aggr = flags & 4;
+    if (stoch) {
+        if (m < G[u]) {
+            if (aggr && Fn[u] > m) atomicMin(Fn + u, m);
+            const int x = F[u];
+            if ((!aggr || x != u) && Fn[x] > m) atomicMin(Fn + x, m);
+        }
+    } else {
+        const int fu = F[u];
+        if (m < fu) {
+            if (fu == G[u]) atomicMin(Fn + fu, m);
+            if (aggr) atomicMin(Fn + u, m);
+        }
+    }
+}
 
 template <int kMode>
 __device__ __forceinline__ void finish_tile_row(int r, int m, bool shared_row, const int *__restrict__ aux,
                                                 const int *__restrict__ F, int *__restrict__ Fn,
-                                                const int *__restrict__ G, int *__restrict__ M) {
-    if (kMode == kPhase) {
+                                                const int *__restrict__ G, int *__restrict__ M, int vflags) {
+    if (kMode == kVariant) {
+        finish_variant(r, m, vflags, F, Fn, G);
+    } else if (kMode == kPhase) {
         int sr = aux[r];
         int u = sr & 0x7fffffff;
         bool sh = shared_row || sr < 0;
@@ -182,8 +238,10 @@ template <int kMode>
 __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     const Tile *__restrict__ tiles, int ntiles, const int *__restrict__ rp, const int *__restrict__ col,
     const int *__restrict__ aux, const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G,
-    int *__restrict__ M) {
+    int *__restrict__ M, int vflags) {
     constexpr bool kBase = kMode == kBaseIota || kMode == kBaseGather;
+    // gathered vector: G, or for a variant the one passed in aux (f or gf)
+    const int *__restrict__ X = kMode == kVariant ? aux : G;
     constexpr bool kNoGather = kMode == kIota || kMode == kBaseIota;
     __shared__ int win[kHookWaves][kRowWin];   // row_ptr[r_lo .. r_hi+1]
     __shared__ int rmin[kHookWaves][kRowWin];  // per-row minimum of this tile
@@ -219,7 +277,7 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     if (!kBase) {
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
-            const int v = kNoGather ? c[j] : G[j < cnt ? c[j] : 0];
+            const int v = kNoGather ? c[j] : X[j < cnt ? c[j] : 0];
             g[j] = j < cnt ? v : INT_MAX;
         }
     }
@@ -293,7 +351,7 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
             int m = rmin[wave][i];
             if (m == INT_MAX) continue;  // empty row
             bool shared_row = (i == 0 && wrow[0] < T.e0) || (i == nrows - 1 && wrow[nrows] > T.e1);
-            finish_tile_row<kMode>(T.r_lo + i, m, shared_row, aux, F, Fn, G, M);
+            finish_tile_row<kMode>(T.r_lo + i, m, shared_row, aux, F, Fn, G, M, vflags);
         }
         return;
     }
@@ -311,7 +369,7 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
                     first_min = cur;
                     first_closed = true;
                 } else {
-                    finish_tile_row<kMode>(row, cur, false, aux, F, Fn, G, M);  // row inside this lane
+                    finish_tile_row<kMode>(row, cur, false, aux, F, Fn, G, M, vflags);  // row inside this lane
                 }
                 do { ++row; nxt = rpw(row + 1); } while (e >= nxt);
                 cur = INT_MAX;
@@ -329,12 +387,12 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     if (first_closed) {
         int m = first_min;
         if (lane > 0 && !first_is_head) m = min(m, prevS);
-        finish_tile_row<kMode>(row0, m, rpw(row0) < T.e0, aux, F, Fn, G, M);
+        finish_tile_row<kMode>(row0, m, rpw(row0) < T.e0, aux, F, Fn, G, M, vflags);
     }
     const bool ends_here = lane == kWave - 1 || next_cnt == 0 || next_head;
     if (ends_here) {
         bool shared_row = rpw(row) < T.e0 || rpw(row + 1) > T.e1;
-        finish_tile_row<kMode>(row, S, shared_row, aux, F, Fn, G, M);
+        finish_tile_row<kMode>(row, S, shared_row, aux, F, Fn, G, M, vflags);
     }
 }
 
@@ -872,6 +930,40 @@ __global__ void k_validate_edges(int64_t m, int n, const int *__restrict__ src, 
         bad |= a < 0 || a >= n || b < 0 || b >= n;
     }
     if (bad) atomicOr(&ctr->status, 1);
+}
+
+// ---------------------------------------------------------------------------
+// End of an iteration of a convergence-ablation variant.
+// Without stochastic hooking the iteration has Alg. 1's second phase, the
+// shortcut f_k[u] = f1[f1[u]] of the hooked vector f1 (k_var_shortcut, into T).
+// k_var_finish then, with fk the new parent vector (Fn, or T after the
+// shortcut): G_k = fk[fk]; counts the vertices whose G (early termination,
+// Sec. 3.4) or f changed; stores fk in Fn when it was built in T; and seeds the
+// next write buffer (the old F buffer) with G_k (stochastic variants, whose
+// pass includes the shortcut) or with fk (Alg. 1's first phase starts from f).
+// ---------------------------------------------------------------------------
+__global__ void k_var_shortcut(int n, const int *__restrict__ Fn, int *__restrict__ T) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) T[u] = Fn[Fn[u]];
+}
+
+__global__ void k_var_finish(int n, const int *__restrict__ fk, int *__restrict__ Fn, int *__restrict__ F,
+                             int *__restrict__ G, IterCounters *__restrict__ ctr, int stoch, int early) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    int changed = 0;
+    for (int u = i; u < n; u += stride) {
+        const int a = fk[u];
+        const int g = fk[a];
+        changed += early ? (g != G[u]) : (a != F[u]);
+        G[u] = g;
+        if (!stoch) Fn[u] = a;
+        F[u] = stoch ? g : a;
+    }
+    // one atomic per wave (every lane reaches this point)
+    const int tot = wave_incl_sum(changed);
+    if (lane_id() == kWave - 1 && tot) atomicAdd(&ctr->packed, (unsigned long long)tot << 32);
 }
 
 __global__ void k_fill(int n, int *__restrict__ x, int v) {

@@ -37,6 +37,12 @@ def test_defaults_and_sizes():
     from paper_1910_05971_amd import binding
     o = binding.default_opts()
     assert o.max_iters == 0 and abs(o.frontier_tau - 0.05) < 1e-7 and o.validate == 0
+    # the last fields read back as set by the library: the struct layouts agree
+    assert o.blocked == -1 and o.binned == -1 and o.bin_shift == 0 and o.sv_flags == 15
+    for bad in (binding.make_opts(sv_flags=16), binding.make_opts(sv_flags=-1), binding.make_opts(bin_shift=16),
+                binding.make_opts(bin_shift=7)):
+        assert binding.workspace_bytes(1000, 5000, bad) == 0
+    assert binding.workspace_bytes(1000, 5000, binding.make_opts(sv_flags="sv3")) > 0
     assert binding.workspace_bytes(-1, 0) == 0
     assert binding.workspace_bytes(10, 2**31) == 0
     a = binding.workspace_bytes(1000, 5000)

@@ -1,0 +1,106 @@
+"""Convergence-ablation variants on the GPU vs the oracle (Sec. 5.2).
+
+fastsv_opts.sv_flags selects which of the four changes of Sec. 3 are applied
+to Algorithm 1 (bit 1 grandparent hooking, 2 stochastic hooking, 4 aggressive
+hooking, 8 early termination).  Every one of the 16 combinations is a
+deterministic Jacobi iteration, so the GPU's iteration count, per-iteration
+termination counts and every iterate must equal oracle_sv_variant's.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import oracle_pins as P
+from paper_1910_05971_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+CAP = 500
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _graphs():
+    n = 300
+    path = P.csr_from_pairs(n, [(i, i + 1) for i in range(n - 1)])
+    star = P.csr_from_pairs(64, [(63, i) for i in range(63)])
+    return [gg.Graph("path300", n, *path, n - 1), gg.Graph("star_last64", 64, *star, 63),
+            gg.rmat(11, 8, seed=71), gg.er(4000, 6000, seed=72), gg.grid(40, 50, 0.55, seed=73)]
+
+
+def _solve(rp, col, **kw):
+    import paper_1910_05971_amd as fs
+    labels, stats, st = fs.cc_csr(rp, col, check=False, **kw)
+    torch.cuda.synchronize()
+    ok = (fs.FASTSV_OK, fs.FASTSV_ENOTCONVERGED) if kw.get("max_iters") else (fs.FASTSV_OK,)
+    assert st in ok, f"status {st}"
+    return labels.cpu().numpy(), stats
+
+
+@pytest.mark.parametrize("flags", list(range(16)))
+def test_variant_trajectories(gpu_ok, flags):
+    for g in _graphs():
+        _say(f"[gpu] sv_flags={flags} {g.name} n={g.n} nnz={g.nnz}")
+        rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr)).cuda()
+        col = torch.from_numpy(np.ascontiguousarray(g.col)).cuda()
+        ref = O.sv_variant(g.n, g.row_ptr, g.col, flags, max_iters=CAP, trace_cap=CAP)
+        assert ref.iterations > 0, (g.name, flags, ref.iterations)
+        got, st = _solve(rp, col, sv_flags=flags, max_iters=CAP)
+        assert np.array_equal(got, ref.f), (g.name, flags)
+        assert st.iterations == ref.iterations, (g.name, flags, st.iterations, ref.iterations)
+        k = min(ref.iterations, 64)
+        assert st.changed_list()[:k] == ref.changed[:k].tolist(), (g.name, flags)
+        for it in range(1, min(ref.iterations, 12) + 1):
+            got_k, _ = _solve(rp, col, sv_flags=flags, max_iters=it)
+            assert np.array_equal(got_k, ref.trace[it - 1]), (g.name, flags, it)
+
+
+def test_named_variants_give_component_minima(gpu_ok):
+    import paper_1910_05971_amd as fs
+    g = gg.c1_er()
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    want = O.uf_labels(g.n, g.row_ptr, g.col)
+    its = {}
+    for name in ("sv1", "sv2", "sv3", "sv4", "sv5"):
+        got, st = _solve(rp, col, sv_flags=name)
+        assert np.array_equal(got, want), name
+        ref = O.sv_variant(g.n, g.row_ptr, g.col, fs.SV_FLAGS[name], max_iters=CAP)
+        assert st.iterations == ref.iterations, (name, st.iterations, ref.iterations)
+        its[name] = st.iterations
+    _say(f"[gpu] C1 iterations {its}")
+    assert its["sv5"] <= its["sv4"]
+
+
+def test_variants_rejected_where_unsupported(gpu_ok):
+    import paper_1910_05971_amd as fs
+    from paper_1910_05971_amd.binding import _ptr
+    b = gg.batch(3, seed=9, max_n=200)
+    dev = torch.device("cuda")
+    vo, eo, rp, col = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (b.vtx_off, b.edge_off, b.row_ptr,
+                                                                                    b.col)]
+    lib = fs.load_library()
+    opts = fs.make_opts(sv_flags=3)
+    labels = torch.empty(rp.numel() - 1, dtype=torch.int32, device=dev)
+    iters = torch.empty(3, dtype=torch.int32, device=dev)
+    import ctypes
+    st = lib.fastsv_cc_batch_csr(fs.context(0), 3, rp.numel() - 1, col.numel(), _ptr(vo), _ptr(eo),
+                                 _ptr(rp), _ptr(col), _ptr(labels), _ptr(iters), None, 0,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(opts), None)
+    assert st == fs.FASTSV_EINVAL
+    # out-of-range flags: no workspace size, and the call itself refuses them
+    rp1 = torch.tensor([0, 1, 2], dtype=torch.int32, device=dev)
+    col1 = torch.tensor([1, 0], dtype=torch.int32, device=dev)
+    with pytest.raises(ValueError):
+        fs.cc_csr(rp1, col1, sv_flags=16)
+    bad = fs.make_opts(sv_flags=16)
+    lab1 = torch.empty(2, dtype=torch.int32, device=dev)
+    st = lib.fastsv_cc_csr(fs.context(0), 2, 2, _ptr(rp1), _ptr(col1), _ptr(lab1), None, 0,
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(bad), None)
+    assert st == fs.FASTSV_EINVAL
