@@ -89,6 +89,15 @@ typedef struct {
                                0 is Algorithm 1; the paper's sv1..sv5 add them in this order
                                (0, 1, 3, 7, 15).  Other than 15: dense pull passes only, no batch
                                entry point (FASTSV_EINVAL there), the server ignores it. */
+    int32_t mode;           /* 0 (default): Jacobi, f read and f_next written (Sec. 2.4): the
+                               iterates and the iteration count are deterministic.  1: one parent
+                               vector read and written concurrently (the form Sec. 2.4 notes is
+                               also correct): passes of hooking with live grandparents and
+                               shortcutting until a pass changes nothing; final labels exact,
+                               iterates and pass count not reproducible.  Mode 1 needs
+                               sv_flags = 15, runs dense pull passes only, and is refused by the
+                               batch entry point.  stats.changed counts the values each pass
+                               lowered. */
 } fastsv_opts;
 
 #define FASTSV_TRACE_ITERS 64

@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("frontier_tau", ctypes.c_float),
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("blocked", ctypes.c_int32), ("block_shift", ctypes.c_int32),
-                ("binned", ctypes.c_int32), ("bin_shift", ctypes.c_int32), ("sv_flags", ctypes.c_int32)]
+                ("binned", ctypes.c_int32), ("bin_shift", ctypes.c_int32), ("sv_flags", ctypes.c_int32),
+                ("mode", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -148,10 +149,13 @@ SV_FLAGS = {"sv1": 0, "sv2": 1, "sv3": 3, "sv4": 7, "sv5": 15}
 
 
 def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None,
-              block_shift=None, binned=None, bin_shift=None, sv_flags=None) -> Opts:
+              block_shift=None, binned=None, bin_shift=None, sv_flags=None, mode=None) -> Opts:
     """blocked, binned: None/"auto" -> automatic, False -> never, True -> always.
-    sv_flags: 0..15 or one of SV_FLAGS' names (None: FastSV)."""
+    sv_flags: 0..15 or one of SV_FLAGS' names (None: FastSV).
+    mode: None/"jacobi"/0 or "async"/1."""
     o = default_opts()
+    if mode is not None:
+        o.mode = {"jacobi": 0, "async": 1}[mode] if isinstance(mode, str) else int(mode)
     if sv_flags is not None:
         o.sv_flags = SV_FLAGS[sv_flags] if isinstance(sv_flags, str) else int(sv_flags)
     if blocked is not None and blocked != "auto":
@@ -199,7 +203,7 @@ def _check_vec(t, name, n=None):
 def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
            max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None, block_shift=None,
-           binned=None, bin_shift=None, sv_flags=None, f_init=None, check=True):
+           binned=None, bin_shift=None, sv_flags=None, mode=None, f_init=None, check=True):
     """Connected components of a symmetric int32 CSR graph resident on the GPU.
 
     Returns (labels, stats); labels[u] is the smallest vertex of u's component.
@@ -219,7 +223,8 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift, sv_flags)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift, sv_flags,
+                     mode)
     if workspace is None:
         wsb = workspace_bytes(n, nnz, opts)
         if wsb == 0:
@@ -265,7 +270,7 @@ def _dev_index(dev):
 
 
 def cc_edges(n: int, src: torch.Tensor, dst: torch.Tensor, *, labels=None, workspace=None, stream=None,
-             max_iters=None, frontier_tau=None, validate=None, timing=None, check=True):
+             max_iters=None, frontier_tau=None, validate=None, timing=None, sv_flags=None, mode=None, check=True):
     """Connected components from an undirected edge list (each edge once, any
     orientation).  Returns (labels, stats)."""
     _check_vec(src, "src")
@@ -275,7 +280,7 @@ def cc_edges(n: int, src: torch.Tensor, dst: torch.Tensor, *, labels=None, works
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, sv_flags=sv_flags, mode=mode)
     lib = load_library()
     workspace, ws, wsb = _workspace(int(lib.fastsv_edges_workspace_bytes(int(n), int(m))), dev, workspace)
     s = stream if stream is not None else torch.cuda.current_stream(dev)

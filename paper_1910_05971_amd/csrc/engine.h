@@ -52,6 +52,8 @@ struct Counters {
 constexpr int kMaxBlocks = 64;
 
 constexpr int kSvFastSV = 15;  // all four changes of Sec. 3: Algorithm 2
+constexpr int kModeJacobi = 0;  // read f, write f_next (Sec. 2.4)
+constexpr int kModeAsync = 1;   // one f read and written concurrently
 
 // ---- binned dense pass geometry ----
 constexpr int kMaxBins = 2048;          // bins per graph (scatter histogram in LDS)
@@ -140,6 +142,7 @@ void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_f
                         int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter,
                         const int *vbase = nullptr, int *gedge = nullptr);
 void launch_fill(hipStream_t s, int n, int *x, int v);
+void launch_fill_iota(hipStream_t s, int n, int *x);
 
 // serving pool helpers
 void launch_srv_status(hipStream_t s, int nslots, const int *slot_vb, const int *lastk, int step, int *gedge,

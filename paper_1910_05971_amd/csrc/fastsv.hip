@@ -91,7 +91,7 @@ LayoutOpts layout_opts(const fastsv_opts &o) {
     lo.cb_shift = o.block_shift;
     lo.bin_mode = o.binned;
     lo.bin_shift = o.bin_shift;
-    if (o.sv_flags != kSvFastSV) {  // ablation variants run the plain pull pass only
+    if (o.sv_flags != kSvFastSV || o.mode == kModeAsync) {  // ablation variants and async: plain passes only
         lo.cb_mode = 0;
         lo.bin_mode = 0;
     }
@@ -335,6 +335,11 @@ void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_f
                        frontier, eoff, ic, write_frontier, lastk, iter, vbase, gedge);
 }
 
+void launch_fill_iota(hipStream_t s, int n, int *x) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, x);
+}
+
 void launch_fill(hipStream_t s, int n, int *x, int v) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, x, v);
@@ -411,6 +416,8 @@ bool opts_ok(const fastsv_opts &o, int64_t n) {
         return false;
     if (o.binned < -1 || o.binned > 1) return false;
     if (o.sv_flags < 0 || o.sv_flags > kSvFastSV) return false;
+    if (o.mode != kModeJacobi && o.mode != kModeAsync) return false;
+    if (o.mode == kModeAsync && o.sv_flags != kSvFastSV) return false;
     if (o.bin_shift != 0 && (o.bin_shift < kBinShiftMin || o.bin_shift > kBinShiftMax)) return false;
     return true;
 }
@@ -526,12 +533,87 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
     return status;
 }
 
+// Asynchronous mode (opts.mode = 1): the caller's label buffer is the single
+// parent vector f; every pass hooks with live grandparents and shortcuts in
+// place, and the loop ends after a pass that changed nothing.  Then every
+// read of that pass saw the final f, so f[u] = f[f[u]] for every u and
+// f[u] <= f[f[v]] = f[v] along every stored entry (both directions): each
+// component is one star whose root, the component minimum (f[w] <= w and f
+// stays in the component), labels it.
+int solve_async(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w, hipStream_t stream,
+                const fastsv_opts &opts, fastsv_stats *stats, int &it) {
+    const int n = P.n;
+    const int64_t ntiles = L.ntiles;
+    if (opts.timing && !ctx->events) {
+        for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+        ctx->events = true;
+    }
+    int *f = P.G;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
+    if (P.f_init) {
+        if (P.f_init != f)
+            HIP_TRY(hipMemcpyAsync(f, P.f_init, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, stream));
+    } else {
+        launch_fill_iota(stream, n, f);
+    }
+    launch_build_tiles(stream, n, 0, 0, (int)P.nnz, P.rp, w.tiles);
+    HIP_TRY(hipGetLastError());
+    int status = FASTSV_OK;
+    it = 0;
+    for (;;) {
+        ++it;
+        IterCounters *ic = &w.ctr->it[it & 1];
+        IterCounters *hc = &ctx->host_ctr->it[it & 1];
+        const int ti = it - 1;
+        const bool timed = opts.timing && ti < FASTSV_TRACE_ITERS;
+        launch_zero_iter(stream, ic);
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
+        if (ntiles > 0)
+            hipLaunchKernelGGL(k_async_hook, dim3(grid_for(ntiles, kHookWaves)), dim3(kWave * kHookWaves), 0, stream,
+                               w.tiles, (int)ntiles, P.rp, P.col, f, ic);
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
+        hipLaunchKernelGGL(k_async_shortcut, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, f, ic);
+        HIP_TRY(hipGetLastError());
+        if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
+        HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const int64_t changed = (int64_t)(hc->packed >> 32);
+        if (stats) {
+            stats->dense_iterations++;
+            if (ti < FASTSV_TRACE_ITERS) {
+                stats->changed[ti] = changed;
+                if (timed) {
+                    float a = 0, b = 0;
+                    HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
+                    HIP_TRY(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+                    stats->ms_hook[ti] = a;
+                    stats->ms_gp[ti] = b;
+                }
+            }
+        }
+        if (changed == 0) break;
+        if (opts.max_iters > 0 && it >= opts.max_iters) {
+            status = FASTSV_ENOTCONVERGED;
+            break;
+        }
+    }
+    if (stats) {
+        stats->iterations = it;
+        stats->num_tiles = (int32_t)ntiles;
+    }
+    return status;
+}
+
 // The iteration loop shared by the entry points (Algorithm 3 with the
 // sparse-frontier switch).  On return `it` holds the iterations executed and
 // `fk` the buffer that holds f after the last iteration.
 int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w, hipStream_t stream,
           const fastsv_opts &opts, fastsv_stats *stats, int &it, int *&fk) {
     if (opts.sv_flags != kSvFastSV) return solve_variant(ctx, P, L, w, stream, opts, stats, it, fk);
+    if (opts.mode == kModeAsync) {
+        fk = P.G;  // f itself, also when capped
+        return solve_async(ctx, P, L, w, stream, opts, stats, it);
+    }
     const int n = P.n;
     const int64_t nnz = P.nnz;
     const int64_t ntiles = L.ntiles;
@@ -744,6 +826,7 @@ fastsv_opts fastsv_default_opts(void) {
     o.binned = -1;
     o.bin_shift = 0;
     o.sv_flags = kSvFastSV;
+    o.mode = kModeJacobi;
     return o;
 }
 
@@ -840,8 +923,9 @@ int cc_csr_impl(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, cons
     int it = 0;
     int *fk = nullptr;
     st = solve(ctx, P, L, w, stream, opts, stats, it, fk);
-    if (st == FASTSV_ENOTCONVERGED) {
-        // labels hold G_k; report the iterate f_k instead
+    if (st == FASTSV_ENOTCONVERGED && fk != labels) {
+        // labels hold G_k; report the iterate f_k instead (the asynchronous
+        // mode's f is the label buffer itself)
         HIP_TRY(hipMemcpyAsync(labels, fk, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
     }
@@ -919,7 +1003,7 @@ int fastsv_cc_edges(fastsv_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     int it = 0;
     int *fk = nullptr;
     st = solve(ctx, P, L, w, stream, opts, stats, it, fk);
-    if (st == FASTSV_ENOTCONVERGED) {
+    if (st == FASTSV_ENOTCONVERGED && fk != labels) {
         HIP_TRY(hipMemcpyAsync(labels, fk, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
     }
@@ -945,7 +1029,8 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
     opts.blocked = 0;  // column ids are local to each graph
     opts.block_shift = 0;
     if (!opts_ok(opts, total_n)) return FASTSV_EINVAL;
-    if (opts.sv_flags != kSvFastSV) return FASTSV_EINVAL;  // per-graph termination is FastSV's
+    // per-graph termination is FastSV's Jacobi one
+    if (opts.sv_flags != kSvFastSV || opts.mode != kModeJacobi) return FASTSV_EINVAL;
     if (stats) memset(stats, 0, sizeof(*stats));
     if (num_graphs == 0) return total_n == 0 && total_nnz == 0 ? FASTSV_OK : FASTSV_EINVAL;
     if (!vtx_off || !edge_off || !rp || !iters || (total_n > 0 && !labels) || (total_nnz > 0 && !col))

@@ -966,6 +966,90 @@ __global__ void k_var_finish(int n, const int *__restrict__ fk, int *__restrict_
     if (lane_id() == kWave - 1 && tot) atomicAdd(&ctr->packed, (unsigned long long)tot << 32);
 }
 
+// ---------------------------------------------------------------------------
+// Asynchronous mode (Sec. 2.4: one parent vector read and written
+// concurrently).  f is deliberately not restrict-qualified: it is read and
+// written by every thread of the pass.
+// Hooking pass: one wave per tile; for each row segment of a lane,
+// m = min over its entries v of the live grandparent f[f[v]]; then
+// f[f[u]] <-min m and f[u] <-min m.  ctr->packed (high 32 bits) counts the
+// atomics that lowered a value.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int async_hook_row(int u, int m, int *f) {
+    int changed = 0;
+    const int x = f[u];
+    if (m < f[x] && atomicMin(f + x, m) > m) ++changed;
+    if (m < f[u] && atomicMin(f + u, m) > m) ++changed;
+    return changed;
+}
+
+__global__ __launch_bounds__(kWave *kHookWaves) void k_async_hook(const Tile *__restrict__ tiles, int ntiles,
+                                                                  const int *__restrict__ rp,
+                                                                  const int *__restrict__ col, int *f,
+                                                                  IterCounters *ctr) {
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int t = blockIdx.x * kHookWaves + wave;
+    if (t >= ntiles) return;  // whole waves leave together
+    const Tile T = tiles[t];
+    const int a = T.e0 + lane * kPerLane;
+    const int cnt = max(0, min(kPerLane, T.e1 - a));
+    int g[kPerLane];
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) g[j] = col[min(a + j, T.e1 - 1)];
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) g[j] = f[g[j]];
+#pragma unroll
+    for (int j = 0; j < kPerLane; ++j) g[j] = f[g[j]];
+    int changed = 0;
+    if (cnt > 0) {
+        int lo = T.r_lo, hi = T.r_hi;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= a) lo = mid;
+            else hi = mid - 1;
+        }
+        int row = lo, nxt = rp[lo + 1], cur = INT_MAX;
+        for (int j = 0; j < cnt; ++j) {
+            const int e = a + j;
+            if (e >= nxt) {
+                changed += async_hook_row(row, cur, f);
+                do { ++row; nxt = rp[row + 1]; } while (e >= nxt);
+                cur = INT_MAX;
+            }
+            cur = min(cur, g[j]);
+        }
+        changed += async_hook_row(row, cur, f);
+    }
+    const int tot = wave_incl_sum(changed);
+    if (lane == kWave - 1 && tot) atomicAdd(&ctr->packed, (unsigned long long)tot << 32);
+}
+
+// Shortcut pass of the asynchronous mode: f[u] <- f[f[u]] where smaller (only
+// thread u writes f[u]; others may read it meanwhile, which is the mode's
+// concurrent reading).  Counts the changes like the hooking pass.
+__global__ void k_async_shortcut(int n, int *f, IterCounters *ctr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    int changed = 0;
+    for (int u = i; u < n; u += stride) {
+        const int p = f[u];
+        const int g = f[p];
+        if (g < p) {
+            f[u] = g;
+            ++changed;
+        }
+    }
+    const int tot = wave_incl_sum(changed);
+    if (lane_id() == kWave - 1 && tot) atomicAdd(&ctr->packed, (unsigned long long)tot << 32);
+}
+
+__global__ void k_iota(int n, int *__restrict__ x) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int stride = gridDim.x * blockDim.x;
+    for (int u = i; u < n; u += stride) x[u] = u;
+}
+
 __global__ void k_fill(int n, int *__restrict__ x, int v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int stride = gridDim.x * blockDim.x;

@@ -38,9 +38,9 @@ def test_defaults_and_sizes():
     o = binding.default_opts()
     assert o.max_iters == 0 and abs(o.frontier_tau - 0.05) < 1e-7 and o.validate == 0
     # the last fields read back as set by the library: the struct layouts agree
-    assert o.blocked == -1 and o.binned == -1 and o.bin_shift == 0 and o.sv_flags == 15
+    assert o.blocked == -1 and o.binned == -1 and o.bin_shift == 0 and o.sv_flags == 15 and o.mode == 0
     for bad in (binding.make_opts(sv_flags=16), binding.make_opts(sv_flags=-1), binding.make_opts(bin_shift=16),
-                binding.make_opts(bin_shift=7)):
+                binding.make_opts(bin_shift=7), binding.make_opts(mode=2), binding.make_opts(mode=1, sv_flags=3)):
         assert binding.workspace_bytes(1000, 5000, bad) == 0
     assert binding.workspace_bytes(1000, 5000, binding.make_opts(sv_flags="sv3")) > 0
     assert binding.workspace_bytes(-1, 0) == 0
