@@ -20,6 +20,10 @@ Also in the same JSON line:
                 distribution, 1% R-MAT scale 20) through the continuous-
                 batching server vs one request at a time: p50/p99 latency and
                 graphs/s, open loop and at saturation
+  extras        on C1, C2 and C3: iterations and time of the convergence
+                ablation sv1..sv5 (Algorithm 1 plus, in turn, the four changes
+                of Sec. 3; sv5 is FastSV) and of the asynchronous mode; and a
+                warm start of C2 from the labels of its first 99% edge draws
 """
 from __future__ import annotations
 
@@ -50,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the convergence ablation, asynchronous mode and warm-start measurements")
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -184,9 +190,78 @@ def bench_solve(args, fs, torch, np):
         check = bool(np.array_equal(labels.cpu().numpy(), want))
     res["cpu_baseline"] = cpu
     res["labels_match_oracle"] = check
+    res["labels"] = labels.cpu().numpy()
+    res["graph"] = g
     del rp, col, labels, ws
     torch.cuda.empty_cache()
     return res
+
+
+def _timed(fn, torch, reps=2):
+    """Best wall time (ms) of reps calls after one untimed call; returns (ms, last result)."""
+    out = fn()
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        best = min(best, 1000.0 * (time.perf_counter() - t))
+    return best, out
+
+
+def bench_extras(fs, torch, np, c2, c2_labels):
+    """The method's other forms on the same inputs: iterations and time of the
+    convergence ablation sv1..sv5 (Algorithm 1 plus, in turn, grandparent,
+    stochastic and aggressive hooking and early termination), the asynchronous
+    mode, and a warm start of C2 after 1% of its edges were added."""
+    from paper_1910_05971_amd import graphgen as gg
+    dev = torch.device("cuda:0")
+    out = {"ablation": {}, "async": {}}
+    for name, g in (("C1 er_n65536_m262144", gg.c1_er()), ("C2 rmat_scale24_ef16", c2),
+                    ("C3 grid_4096x4096_p0.55", gg.c3_grid())):
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        col = torch.from_numpy(g.col).to(dev)
+        ws = torch.empty(fs.workspace_bytes(g.n, g.nnz) + 256, dtype=torch.uint8, device=dev)
+        row, ref = {}, None
+        for vname, flags in fs.SV_FLAGS.items():
+            ms, (lab, st) = _timed(lambda: fs.cc_csr(rp, col, workspace=ws, sv_flags=flags), torch)
+            lab = lab.cpu().numpy()
+            ref = lab if ref is None else ref
+            row[vname] = {"iterations": st.iterations, "ms": ms, "labels_equal_sv1": bool(np.array_equal(lab, ref))}
+        out["ablation"][name] = row
+        ms, (lab, st) = _timed(lambda: fs.cc_csr(rp, col, workspace=ws, mode="async"), torch)
+        out["async"][name] = {"passes": st.iterations, "ms": ms, "jacobi_ms": row["sv5"]["ms"],
+                              "jacobi_iterations": row["sv5"]["iterations"],
+                              "labels_equal_jacobi": bool(np.array_equal(lab.cpu().numpy(), ref))}
+        log(f"extras {name}: " + ", ".join(f"{k} {v['iterations']} it {v['ms']:.2f} ms" for k, v in row.items())
+            + f"; async {st.iterations} passes {ms:.2f} ms")
+        del rp, col, ws
+        torch.cuda.empty_cache()
+    # warm start: C2 without the last 1% of its edge draws, solved; then the
+    # full C2 from those labels, against solving it from scratch
+    src, dst = gg.rmat_edges(24, 16, seed=2)
+    keep = int(src.shape[0] * 0.99)
+    rp99, col99 = gg.csr_from_edges(1 << 24, src[:keep], dst[:keep])
+    del src, dst
+    rp = torch.from_numpy(rp99).to(dev)
+    col = torch.from_numpy(col99).to(dev)
+    lab99, _ = fs.cc_csr(rp, col)
+    torch.cuda.synchronize()
+    del rp, col
+    rp = torch.from_numpy(c2.row_ptr).to(dev)
+    col = torch.from_numpy(c2.col).to(dev)
+    ws = torch.empty(fs.workspace_bytes(c2.n, c2.nnz) + 256, dtype=torch.uint8, device=dev)
+    ms_warm, (lab, st_w) = _timed(lambda: fs.cc_csr(rp, col, workspace=ws, f_init=lab99), torch)
+    ok = bool(np.array_equal(lab.cpu().numpy(), c2_labels))
+    ms_cold, (_, st_c) = _timed(lambda: fs.cc_csr(rp, col, workspace=ws), torch)
+    out["warm_start"] = {"workload": "rmat_scale24_ef16 from the labels of its first 99% edge draws",
+                         "warm_ms": ms_warm, "warm_iterations": st_w.iterations, "cold_ms": ms_cold,
+                         "cold_iterations": st_c.iterations, "labels_equal_cold": ok}
+    log(f"extras warm start: {ms_warm:.2f} ms / {st_w.iterations} it vs cold {ms_cold:.2f} ms / {st_c.iterations} it")
+    del rp, col, ws, lab99
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(fs, torch, np):
@@ -299,6 +374,8 @@ def main():
     }
     if res["cpu_baseline"]:
         out["cpu_baseline"] = res["cpu_baseline"]
+    if not args.no_extras and args.workload == "rmat24":
+        out["extras"] = bench_extras(fs, torch, np, res["graph"], res["labels"])
     if not args.no_batch:
         out["batched"] = bench_batch(fs, torch, np)
     if not args.no_serve:
