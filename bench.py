@@ -316,16 +316,17 @@ def bench_serve(args, torch, np):
         return float(np.percentile(lat, 50) * 1e3), float(np.percentile(lat, 99) * 1e3)
 
     def server():
-        return serving.Server(max_vertices=8_000_000, max_entries=150_000_000, max_slots=512, validate=False)
+        # pool for the trace's working set: about 1.3 GB of CSR and labels state
+        return serving.Server(max_vertices=16_000_000, max_entries=320_000_000, max_slots=2048, validate=False)
 
     # warm both paths
     srv = server()
-    serving.run_open_loop(srv, graphs[:64], np.zeros(64))
+    serving.run_open_loop(srv, graphs[:64], np.zeros(64), mapped=True)
     srv.close()
     serving.run_plain(graphs[:64], np.zeros(64))
     for mode, arr in (("open_loop", tr.arrivals), ("saturation", np.zeros_like(tr.arrivals))):
         srv = server()
-        lat, span, _ = serving.run_open_loop(srv, graphs, arr)
+        lat, span, _ = serving.run_open_loop(srv, graphs, arr, mapped=True)
         s = srv.stats()
         srv.close()
         p50, p99 = pct(lat)

@@ -285,8 +285,30 @@ int fastsv_server_submit(fastsv_server *srv, int32_t n, int64_t nnz, const int32
                          const int32_t *h_col_idx, int32_t *h_labels_out, int32_t *h_iters_out,
                          uint64_t *ticket);
 
-/* Admit what fits, run one iteration for all resident graphs, retire the
- * converged ones.  Reports how many graphs are resident and queued after it. */
+/* The same for a caller whose h_row_ptr and h_col_idx are page-locked host
+ * memory mapped into the device address space at the same address (memory
+ * from hipHostMalloc on ROCm): the per-request query of the pointers'
+ * attributes is skipped.  Passing other memory here is undefined. */
+int fastsv_server_submit_mapped(fastsv_server *srv, int32_t n, int64_t nnz, const int32_t *h_row_ptr,
+                                const int32_t *h_col_idx, int32_t *h_labels_out, int32_t *h_iters_out,
+                                uint64_t *ticket);
+
+/* count requests in one call, as count calls of fastsv_server_submit (mapped
+ * = 0) or fastsv_server_submit_mapped (mapped = 1); request i is (n[i],
+ * nnz[i], h_row_ptr[i], h_col_idx[i], h_labels_out[i], &h_iters_out[i]) and
+ * gets tickets[i] (h_iters_out and tickets may be NULL).  Stops at the first
+ * request that is refused and returns its status; *n_accepted says how many
+ * were queued. */
+int fastsv_server_submit_batch(fastsv_server *srv, int32_t count, const int32_t *n, const int64_t *nnz,
+                               const int32_t *const *h_row_ptr, const int32_t *const *h_col_idx,
+                               int32_t *const *h_labels_out, int32_t *h_iters_out, uint64_t *tickets,
+                               int32_t mapped, int32_t *n_accepted);
+
+/* Admit what fits (at most about 128 MB of graph data per step once one graph
+ * is in, so that admission copies overlap the iterations), run one iteration
+ * for all resident graphs, retire the converged ones.  Graphs admitted while
+ * others are resident start iterating at the next step.  Reports how many
+ * graphs are resident and queued after it. */
 int fastsv_server_step(fastsv_server *srv, int32_t *n_resident, int32_t *n_queued);
 
 /* Up to cap tickets completed since the last poll, oldest first. */

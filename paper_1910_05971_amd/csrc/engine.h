@@ -85,6 +85,15 @@ struct SrvNew {
     int pad;
 };
 
+// One workgroup's share of the placement of newly admitted graphs.
+struct PlaceChunk {
+    int k;      // graph of the step's admission list
+    int part;   // 0: vertex slots 0..n (row pointers, init); 1: column ids
+    int start, count;
+};
+constexpr int kPlaceChunk = 1 << 14;  // items per placement workgroup
+constexpr int kPlaceUnroll = 8;
+
 // Exclusive-scan geometry.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
@@ -149,7 +158,7 @@ void launch_srv_status(hipStream_t s, int nslots, const int *slot_vb, const int 
                        int *out_flag, int *out_edges);
 void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
                             const Tile *pool_tiles, Tile *step_tiles, int *mark, int step);
-void launch_srv_place(hipStream_t s, int nnew, int64_t items, const SrvNew *desc, const int *item_off,
+void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
                       const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
                       int *lastk);
 void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,

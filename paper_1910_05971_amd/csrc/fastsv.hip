@@ -359,12 +359,12 @@ void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const Sr
                        tile_off, pool_tiles, step_tiles, mark, step);
 }
 
-void launch_srv_place(hipStream_t s, int nnew, int64_t items, const SrvNew *desc, const int *item_off,
+void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
                       const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
                       int *lastk) {
-    if (nnew <= 0 || items <= 0) return;
-    hipLaunchKernelGGL(k_srv_place, dim3(grid_for(items, 256, 8192)), dim3(256), 0, s, nnew, desc, item_off, srcs,
-                       rp, col, F0, F1, G, M, vbase, lastk);
+    if (nchunks <= 0) return;
+    hipLaunchKernelGGL(k_srv_place, dim3(nchunks), dim3(256), 0, s, chunks, desc, srcs, rp, col, F0, F1, G, M, vbase,
+                       lastk);
 }
 
 void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,

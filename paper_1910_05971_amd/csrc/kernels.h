@@ -1197,29 +1197,45 @@ __global__ void k_srv_dense_tiles(int ndense, const SrvNew *__restrict__ desc, c
 // are numbered across the batch; item_off is the exclusive prefix of the
 // per-graph item counts (2(n+1) + nnz).
 
-__global__ void k_srv_place(int nnew, const SrvNew *__restrict__ desc, const int *__restrict__ item_off,
-                            const int *const *__restrict__ srcs, int *__restrict__ rp, int *__restrict__ col,
-                            int *__restrict__ F0, int *__restrict__ F1, int *__restrict__ G, int *__restrict__ M,
-                            int *__restrict__ vbase, int *__restrict__ lastk) {
-    // srcs[2k], srcs[2k+1]: device-visible row_ptr and col of new graph k
-    // (device staging, or page-locked host memory read directly)
-    const int64_t total = item_off[nnew];
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total;
-         x += (int64_t)gridDim.x * blockDim.x) {
-        const int k = find_owner(item_off, nnew, x);
-        const SrvNew d = desc[k];
-        int i = (int)(x - item_off[k]);
-        if (i <= d.n) {
-            rp[d.vb + i] = srcs[2 * k][i] + d.eb;
-        } else if (i <= 2 * d.n + 1) {
-            i -= d.n + 1;
+// Placement of newly admitted graphs: one workgroup per chunk of the
+// per-step chunk table.  Part 0 of graph k covers its vertex slots 0..n
+// (row pointer rebased to the pool, neutral-state init); part 1 its column ids
+// (only when they were not copied by DMA).  Sources are device-visible: the
+// staging buffer, or page-locked host memory read in place.
+__global__ __launch_bounds__(256) void k_srv_place(const PlaceChunk *__restrict__ chunks,
+                                                   const SrvNew *__restrict__ desc,
+                                                   const int *const *__restrict__ srcs, int *__restrict__ rp,
+                                                   int *__restrict__ col, int *__restrict__ F0, int *__restrict__ F1,
+                                                   int *__restrict__ G, int *__restrict__ M, int *__restrict__ vbase,
+                                                   int *__restrict__ lastk) {
+    const PlaceChunk c = chunks[blockIdx.x];
+    const SrvNew d = desc[c.k];
+    const int end = c.start + c.count;
+    if (c.part == 0) {
+        const int *__restrict__ srp = srcs[2 * c.k];
+        for (int i = c.start + threadIdx.x; i < end; i += blockDim.x) {
             const int u = d.vb + i;
+            rp[u] = srp[i] + d.eb;
             F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
             vbase[u] = d.vb;
             lastk[u] = 0;
-        } else {
-            i -= 2 * (d.n + 1);
-            col[d.eb + i] = srcs[2 * k + 1][i];
+        }
+        return;
+    }
+    // column ids: kPlaceUnroll independent loads in flight per thread
+    const int *__restrict__ scol = srcs[2 * c.k + 1];
+    int *__restrict__ dst = col + d.eb;
+    for (int base = c.start + threadIdx.x; base < end; base += kPlaceUnroll * blockDim.x) {
+        int v[kPlaceUnroll];
+#pragma unroll
+        for (int q = 0; q < kPlaceUnroll; ++q) {
+            const int idx = base + q * blockDim.x;
+            v[q] = scol[idx < end ? idx : c.start];
+        }
+#pragma unroll
+        for (int q = 0; q < kPlaceUnroll; ++q) {
+            const int idx = base + q * blockDim.x;
+            if (idx < end) dst[idx] = v[q];
         }
     }
 }

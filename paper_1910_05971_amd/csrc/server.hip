@@ -32,60 +32,16 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <new>
 #include <vector>
 
 #include "engine.h"
 #include "fastsv.h"
+#include "range_alloc.h"
 
 using namespace fsv;
 
 namespace {
-
-// First-fit allocator over [0, cap) with coalescing of freed ranges.
-class RangeAlloc {
-public:
-    explicit RangeAlloc(int64_t cap = 0) { reset(cap); }
-    void reset(int64_t cap) {
-        free_.clear();
-        cap_ = cap;
-        if (cap > 0) free_[0] = cap;
-    }
-    int64_t alloc(int64_t len) {
-        if (len <= 0) return 0;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= len) {
-                int64_t start = it->first, rest = it->second - len;
-                free_.erase(it);
-                if (rest > 0) free_[start + len] = rest;
-                return start;
-            }
-        }
-        return -1;
-    }
-    void release(int64_t start, int64_t len) {
-        if (len <= 0) return;
-        auto it = free_.emplace(start, len).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    int64_t capacity() const { return cap_; }
-
-private:
-    std::map<int64_t, int64_t> free_;
-    int64_t cap_ = 0;
-};
 
 struct Request {
     uint64_t ticket;
@@ -97,7 +53,16 @@ struct Request {
     int32_t *iters_out;
 };
 
-enum SlotState : int { kFree = 0, kRunning = 1, kRetiring = 2 };
+// kStaged: placed (or being placed) on the copy stream, runs from the next step
+enum SlotState : int { kFree = 0, kRunning = 1, kRetiring = 2, kStaged = 3 };
+
+// pinned requests at least this large have their column ids copied by the DMA
+// engine straight into the pool; smaller ones are read by the placement kernel
+constexpr int64_t kSrvDmaMinEntries = 1 << 18;
+// bytes of graph data admitted per step (once at least one graph is admitted):
+// a step's transfers then take about as long as its compute, and the copy
+// stream works on the next graphs while the resident ones iterate
+constexpr int64_t kSrvStepAdmitBytes = int64_t(128) << 20;
 
 struct Slot {
     int state = kFree;
@@ -115,9 +80,16 @@ inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct PoolLayout {
     size_t rp, col, F0, F1, G, M, vbase, lastk, frontier, eoff, tiles, ctr, slot_vb, slot_n, flags, stage, desc,
-        off_a, off_b, out, desc_ret, off_ret, step_tiles, gmode, gedge, out_edges, desc_dense, off_dense, srcs,
+        chunks, off_b, out, desc_ret, off_ret, step_tiles, gmode, gedge, out_edges, desc_dense, off_dense, srcs,
         total;
 };
+
+// Placement chunks one step can need: every admitted graph's vertex slots and
+// column ids, cut into kPlaceChunk items (at most S graphs, V + S vertex slots
+// and E entries in the pool).
+inline int64_t max_place_chunks(int64_t V, int64_t E, int64_t S) {
+    return (V + S + E) / kPlaceChunk + 2 * S + 2;
+}
 
 // T: tiles of one step's new graphs; the staging buffer holds the row_ptr and
 // col of all graphs admitted in one step (at most V + E ints) and the labels
@@ -144,7 +116,7 @@ PoolLayout pool_layout(int64_t V, int64_t E, int64_t T, int64_t S) {
     L.flags = take(sizeof(int) * (size_t)S);
     L.stage = take(sizeof(int) * (size_t)(V + 1 + E));
     L.desc = take(sizeof(SrvNew) * (size_t)S);
-    L.off_a = take(sizeof(int) * (size_t)(S + 1));
+    L.chunks = take(sizeof(PlaceChunk) * (size_t)max_place_chunks(V, E, S));
     L.off_b = take(sizeof(int) * (size_t)(S + 1));
     L.out = take(v4);
     L.desc_ret = take(sizeof(SrvNew) * (size_t)S);
@@ -166,25 +138,39 @@ struct fastsv_server {
     fastsv_ctx *ctx = nullptr;
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t cs = nullptr;            // placement stream: admission overlaps the compute of a step
+    hipStream_t ds = nullptr;            // DMA stream for large column arrays, beside the placement
+    hipEvent_t ev_placed[2] = {};        // on cs: the graphs admitted at a step are in the pool
+    hipEvent_t ev_dma[2] = {};           // on ds: their DMA'd column arrays are too
+    bool staged_pending = false;         // graphs placed at the previous step wait for their first iteration
     fastsv_opts opts{};
     int64_t V = 0, E = 0, T = 0;
     int S = 0;
     char *pool = nullptr;
     PoolLayout L{};
-    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *slot_vb, *slot_n, *flags, *stage, *off_a, *off_b,
+    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *slot_vb, *slot_n, *flags, *stage, *off_b,
         *out, *off_ret, *gmode, *gedge, *out_edges, *off_dense;
+    PlaceChunk *chunks;
     SrvNew *desc, *desc_ret, *desc_dense;
     const int **srcs;
     Tile *tiles, *step_tiles;
     Counters *ctr;
-    // pinned host mirrors
-    int *h_slot_vb = nullptr, *h_slot_n = nullptr, *h_flags = nullptr, *h_off_a = nullptr,
-        *h_off_b = nullptr, *h_out = nullptr, *h_off_ret = nullptr, *h_edges = nullptr, *h_off_dense = nullptr;
-    SrvNew *h_desc = nullptr, *h_desc_ret = nullptr, *h_desc_dense = nullptr;
-    const int **h_srcs = nullptr;
+    // pinned host mirrors; the admission ones are double-buffered by step
+    // parity, since the copy stream may still read one step's while the host
+    // prepares the next
+    int *h_slot_vb = nullptr, *h_slot_n = nullptr, *h_flags = nullptr,
+        *h_off_b2[2] = {}, *h_out = nullptr, *h_off_ret = nullptr, *h_edges = nullptr, *h_off_dense = nullptr;
+    PlaceChunk *h_chunks2[2] = {};
+    SrvNew *h_desc2[2] = {}, *h_desc_ret = nullptr, *h_desc_dense = nullptr;
+    const int **h_srcs2[2] = {};
     RangeAlloc va, ea, ta;
+    // ranges of graphs retired in the current step: allocatable from the next
+    // step on, when their reset (compute stream) has completed, so that the
+    // copy stream never waits for the compute stream
+    std::vector<std::pair<int64_t, int64_t>> rel_v, rel_e, rel_t;
     std::deque<Request> queue;
     std::vector<Slot> slots;
+    std::vector<int> free_slots;  // stack of free slot indices
     std::vector<int> flag_slot;  // slot of each entry of h_flags
     std::deque<uint64_t> done;
     int step = 0;
@@ -274,7 +260,7 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     s->flags = reinterpret_cast<int *>(p + s->L.flags);
     s->stage = reinterpret_cast<int *>(p + s->L.stage);
     s->desc = reinterpret_cast<SrvNew *>(p + s->L.desc);
-    s->off_a = reinterpret_cast<int *>(p + s->L.off_a);
+    s->chunks = reinterpret_cast<PlaceChunk *>(p + s->L.chunks);
     s->off_b = reinterpret_cast<int *>(p + s->L.off_b);
     s->out = reinterpret_cast<int *>(p + s->L.out);
     s->desc_ret = reinterpret_cast<SrvNew *>(p + s->L.desc_ret);
@@ -290,15 +276,28 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     // and is written at most once per step
     bool ok = pinned(&s->h_out, (size_t)s->V) && pinned(&s->h_desc_ret, max_slots) &&
               pinned(&s->h_edges, max_slots) && pinned(&s->h_desc_dense, max_slots) &&
-              pinned(&s->h_off_dense, max_slots + 1) && pinned(&s->h_srcs, 2 * (size_t)max_slots) &&
-              pinned(&s->h_off_ret, max_slots + 1) && pinned(&s->h_slot_vb, max_slots) && pinned(&s->h_slot_n, max_slots) && pinned(&s->h_flags, max_slots) &&
-              pinned(&s->h_desc, max_slots) &&
-              pinned(&s->h_off_a, max_slots + 1) && pinned(&s->h_off_b, max_slots + 1);
+              pinned(&s->h_off_dense, max_slots + 1) && pinned(&s->h_off_ret, max_slots + 1) &&
+              pinned(&s->h_slot_vb, max_slots) && pinned(&s->h_slot_n, max_slots) && pinned(&s->h_flags, max_slots);
+    for (int b = 0; b < 2 && ok; ++b)
+        ok = pinned(&s->h_srcs2[b], 2 * (size_t)max_slots) && pinned(&s->h_desc2[b], max_slots) &&
+             pinned(&s->h_chunks2[b], (size_t)max_place_chunks(s->V, s->E, s->S)) &&
+             pinned(&s->h_off_b2[b], max_slots + 1);
     if (!ok) { fastsv_server_destroy(s); return FASTSV_ENOMEM; }
+    // copy stream at the default priority, and its events
+    if (hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->ds, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_placed[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_placed[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_dma[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_dma[1], hipEventDisableTiming) != hipSuccess) {
+        fastsv_server_destroy(s);
+        return FASTSV_EHIP;
+    }
     s->va.reset(s->V);
     s->ea.reset(s->E);
     s->ta.reset(s->T);
     s->slots.assign(max_slots, Slot{});
+    for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     // neutral state everywhere: every pool vertex its own root, empty rows
     launch_fill(stream, (int)(s->V + 1), s->rp, 0);
     launch_init(stream, (int)s->V, s->F[0], s->F[1], s->G, s->M, 0);
@@ -320,16 +319,28 @@ void fastsv_server_destroy(fastsv_server *s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->cs) (void)hipStreamSynchronize(s->cs);
+    if (s->ds) (void)hipStreamSynchronize(s->ds);
     if (s->pool) (void)hipFree(s->pool);
-    for (void *h : {(void *)s->h_slot_vb, (void *)s->h_slot_n, (void *)s->h_flags, (void *)s->h_desc, (void *)s->h_off_a, (void *)s->h_off_b, (void *)s->h_out,
+    for (void *h : {(void *)s->h_slot_vb, (void *)s->h_slot_n, (void *)s->h_flags, (void *)s->h_out,
                     (void *)s->h_desc_ret, (void *)s->h_off_ret, (void *)s->h_edges, (void *)s->h_desc_dense,
-                    (void *)s->h_off_dense, (void *)s->h_srcs})
+                    (void *)s->h_off_dense, (void *)s->h_desc2[0], (void *)s->h_desc2[1], (void *)s->h_chunks2[0],
+                    (void *)s->h_chunks2[1], (void *)s->h_off_b2[0], (void *)s->h_off_b2[1], (void *)s->h_srcs2[0],
+                    (void *)s->h_srcs2[1]})
         if (h) (void)hipHostFree(h);
+    for (hipEvent_t e : {s->ev_placed[0], s->ev_placed[1], s->ev_dma[0], s->ev_dma[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (s->cs) (void)hipStreamDestroy(s->cs);
+    if (s->ds) (void)hipStreamDestroy(s->ds);
     delete s;
 }
 
-int fastsv_server_submit(fastsv_server *s, int32_t n, int64_t nnz, const int32_t *h_row_ptr, const int32_t *h_col,
-                         int32_t *h_labels_out, int32_t *h_iters_out, uint64_t *ticket) {
+}  // extern "C"
+
+namespace {
+
+int submit_impl(fastsv_server *s, int32_t n, int64_t nnz, const int32_t *h_row_ptr, const int32_t *h_col,
+                int32_t *h_labels_out, int32_t *h_iters_out, uint64_t *ticket, bool mapped) {
     if (!s || n < 0 || nnz < 0 || !h_row_ptr || (nnz > 0 && !h_col) || (n > 0 && !h_labels_out)) return FASTSV_EINVAL;
     if ((int64_t)n + 1 > s->V || nnz > s->E || (nnz + kTileEntries - 1) / kTileEntries > s->T) return FASTSV_ENOMEM;
     // with opts.validate, a host-side check of the CSR before it is ever
@@ -357,9 +368,40 @@ int fastsv_server_submit(fastsv_server *s, int32_t n, int64_t nnz, const int32_t
     }
     r.rp = h_row_ptr;
     r.col = h_col;
-    r.drp = device_view(h_row_ptr);
-    r.dcol = nnz > 0 ? device_view(h_col) : r.drp;
+    r.drp = mapped ? h_row_ptr : device_view(h_row_ptr);
+    r.dcol = nnz > 0 ? (mapped ? h_col : device_view(h_col)) : r.drp;
     s->queue.push_back(r);
+    return FASTSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fastsv_server_submit(fastsv_server *s, int32_t n, int64_t nnz, const int32_t *h_row_ptr, const int32_t *h_col,
+                         int32_t *h_labels_out, int32_t *h_iters_out, uint64_t *ticket) {
+    return submit_impl(s, n, nnz, h_row_ptr, h_col, h_labels_out, h_iters_out, ticket, false);
+}
+
+int fastsv_server_submit_mapped(fastsv_server *s, int32_t n, int64_t nnz, const int32_t *h_row_ptr,
+                                const int32_t *h_col, int32_t *h_labels_out, int32_t *h_iters_out, uint64_t *ticket) {
+    return submit_impl(s, n, nnz, h_row_ptr, h_col, h_labels_out, h_iters_out, ticket, true);
+}
+
+int fastsv_server_submit_batch(fastsv_server *s, int32_t count, const int32_t *n, const int64_t *nnz,
+                               const int32_t *const *h_row_ptr, const int32_t *const *h_col,
+                               int32_t *const *h_labels_out, int32_t *h_iters_out, uint64_t *tickets,
+                               int32_t mapped, int32_t *n_accepted) {
+    if (!s || count < 0 || (count > 0 && (!n || !nnz || !h_row_ptr || !h_col || !h_labels_out)) || !n_accepted)
+        return FASTSV_EINVAL;
+    *n_accepted = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const int st = submit_impl(s, n[i], nnz[i], h_row_ptr[i], h_col[i], h_labels_out[i],
+                                   h_iters_out ? h_iters_out + i : nullptr, tickets ? tickets + i : nullptr,
+                                   mapped != 0);
+        if (st != FASTSV_OK) return st;
+        *n_accepted = i + 1;
+    }
     return FASTSV_OK;
 }
 
@@ -367,9 +409,34 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     if (!s) return FASTSV_EINVAL;
     SRV_TRY(hipSetDevice(s->device));
     hipStream_t st = s->stream;
+    hipStream_t cs = s->cs;
     const int step = ++s->step;
+    const int par = step & 1;
     IterCounters *ic_front = &s->ctr->it[(step + 1) & 1];  // frontier left by the previous step
     IterCounters *ic = &s->ctr->it[step & 1];
+
+    // 0. graphs placed by the previous step run from this one on, once their
+    //    placement (copy stream) is complete
+    int nrunning = 0;
+    if (s->staged_pending) {
+        SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[par ^ 1], 0));
+        SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[par ^ 1], 0));
+        for (Slot &sl : s->slots)
+            if (sl.state == kStaged) {
+                sl.state = kRunning;
+                sl.admit_step = step;
+            }
+        s->staged_pending = false;
+    }
+    for (const Slot &sl : s->slots) nrunning += sl.state == kRunning;
+    // ranges retired by the previous step (its reset finished before that
+    // step's synchronisation returned)
+    for (auto &r : s->rel_v) s->va.release(r.first, r.second);
+    for (auto &r : s->rel_e) s->ea.release(r.first, r.second);
+    for (auto &r : s->rel_t) s->ta.release(r.first, r.second);
+    s->rel_v.clear();
+    s->rel_e.clear();
+    s->rel_t.clear();
 
     // 1. retire the graphs found converged by the previous step (their labels
     //    reach the callers after this step's synchronisation)
@@ -392,23 +459,31 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
                           s->lastk);
         SRV_TRY(hipGetLastError());
         SRV_TRY(hipMemcpyAsync(s->h_out, s->out, sizeof(int) * (size_t)ret_rows, hipMemcpyDeviceToHost, st));
-        // the ranges can be handed out again: everything below runs after the reset on the stream
         for (int j = 0; j < nret; ++j) {
             Slot &sl = s->slots[retired[j]];
-            s->va.release(sl.vb, sl.n + 1);
-            s->ea.release(sl.eb, sl.nnz);
-            s->ta.release(sl.tb, sl.ntiles);
+            s->rel_v.emplace_back(sl.vb, sl.n + 1);
+            s->rel_e.emplace_back(sl.eb, sl.nnz);
+            s->rel_t.emplace_back(sl.tb, sl.ntiles);
         }
     }
 
-    // 2. admission
-    int nnew = 0, new_rows = 0;
-    int64_t items = 0, staged = 0;
-    while (!s->queue.empty()) {
-        int k = -1;
-        for (int i = 0; i < s->S; ++i)
-            if (s->slots[i].state == kFree) { k = i; break; }
-        if (k < 0) break;
+    // 2. admission, placed on the copy stream while this step computes.  The
+    //    new vertex ranges hold the same values as the neutral state the
+    //    resident graphs' whole-range kernels may touch (F = G = M = u,
+    //    lastk = 0), so the placement and those kernels cannot disturb each
+    //    other.  With nothing else resident the new graphs run in this step.
+    SrvNew *h_desc = s->h_desc2[par];
+    const int **h_srcs = s->h_srcs2[par];
+    int *h_off_b = s->h_off_b2[par];
+    PlaceChunk *h_chunks = s->h_chunks2[par];
+    int nnew = 0, new_rows = 0, nchunks = 0;
+    int64_t staged = 0;
+    std::vector<int> admitted;
+    const bool same_step = nrunning == 0;
+    int64_t admit_bytes = 0;
+    while (!s->queue.empty() && (nnew == 0 || admit_bytes < kSrvStepAdmitBytes)) {
+        if (s->free_slots.empty()) break;
+        const int k = s->free_slots.back();
         Request &r = s->queue.front();
         const int ntiles = (int)((r.nnz + kTileEntries - 1) / kTileEntries);
         const int64_t vb = s->va.alloc(r.n + 1);
@@ -417,8 +492,9 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         if (eb < 0) { s->va.release(vb, r.n + 1); break; }
         const int64_t tb = s->ta.alloc(ntiles);
         if (tb < 0) { s->va.release(vb, r.n + 1); s->ea.release(eb, r.nnz); break; }
+        s->free_slots.pop_back();
         Slot &sl = s->slots[k];
-        sl.state = kRunning;
+        sl.state = kStaged;
         sl.ticket = r.ticket;
         sl.n = r.n;
         sl.nnz = r.nnz;
@@ -427,47 +503,64 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         sl.tb = (int)tb;
         sl.ntiles = ntiles;
         sl.fedge = 0;
-        sl.admit_step = step;
+        sl.admit_step = step + 1;
         sl.labels_out = r.labels_out;
         sl.iters_out = r.iters_out;
+        admitted.push_back(k);
         SrvNew d{(int)vb, (int)eb, r.n, (int)r.nnz, (int)staged, (int)(staged + r.n + 1), (int)tb, 0};
-        if (r.drp && r.dcol) {
-            // page-locked: the placement kernel reads the host arrays directly
-            s->h_srcs[2 * nnew] = r.drp;
-            s->h_srcs[2 * nnew + 1] = r.dcol;
+        // row pointers: read in place when page-locked, else staged by DMA;
+        // column ids: by DMA straight into the pool when pageable or large,
+        // else read in place by the placement kernel
+        const bool col_dma = r.nnz > 0 && (!r.dcol || r.nnz >= kSrvDmaMinEntries);
+        if (r.drp) {
+            h_srcs[2 * nnew] = r.drp;
         } else {
             SRV_TRY(hipMemcpyAsync(s->stage + d.s_rp, r.rp, sizeof(int) * (size_t)(r.n + 1), hipMemcpyHostToDevice,
-                                   st));
-            if (r.nnz > 0)
-                SRV_TRY(hipMemcpyAsync(s->stage + d.s_col, r.col, sizeof(int) * (size_t)r.nnz, hipMemcpyHostToDevice,
-                                       st));
-            s->h_srcs[2 * nnew] = s->stage + d.s_rp;
-            s->h_srcs[2 * nnew + 1] = s->stage + d.s_col;
-            staged += r.n + 1 + r.nnz;
+                                   cs));
+            h_srcs[2 * nnew] = s->stage + d.s_rp;
+            staged += r.n + 1;
         }
-        s->h_desc[nnew] = d;
-        s->h_off_a[nnew] = (int)items;
-        s->h_off_b[nnew] = new_rows;
-        items += 2 * ((int64_t)r.n + 1) + r.nnz;
+        if (col_dma)
+            SRV_TRY(hipMemcpyAsync(s->col + eb, r.col, sizeof(int) * (size_t)r.nnz, hipMemcpyHostToDevice, s->ds));
+        h_srcs[2 * nnew + 1] = col_dma ? nullptr : r.dcol;
+        h_desc[nnew] = d;
+        h_off_b[nnew] = new_rows;
+        for (int c0 = 0; c0 <= r.n; c0 += kPlaceChunk)
+            h_chunks[nchunks++] = PlaceChunk{nnew, 0, c0, std::min(kPlaceChunk, r.n + 1 - c0)};
+        if (!col_dma)
+            for (int64_t c0 = 0; c0 < r.nnz; c0 += kPlaceChunk)
+                h_chunks[nchunks++] = PlaceChunk{nnew, 1, (int)c0, (int)std::min<int64_t>(kPlaceChunk, r.nnz - c0)};
+        admit_bytes += sizeof(int) * ((int64_t)r.n + 1 + r.nnz);
         new_rows += r.n;
         ++nnew;
         s->queue.pop_front();
         s->st.admitted++;
     }
     if (nnew > 0) {
-        s->h_off_a[nnew] = (int)items;
-        s->h_off_b[nnew] = new_rows;
-        SRV_TRY(hipMemcpyAsync(s->desc, s->h_desc, sizeof(SrvNew) * nnew, hipMemcpyHostToDevice, st));
-        SRV_TRY(hipMemcpyAsync(s->srcs, s->h_srcs, sizeof(void *) * 2 * nnew, hipMemcpyHostToDevice, st));
-        SRV_TRY(hipMemcpyAsync(s->off_a, s->h_off_a, sizeof(int) * (nnew + 1), hipMemcpyHostToDevice, st));
-        SRV_TRY(hipMemcpyAsync(s->off_b, s->h_off_b, sizeof(int) * (nnew + 1), hipMemcpyHostToDevice, st));
-        launch_srv_place(st, nnew, items, s->desc, s->off_a, s->srcs, s->rp, s->col, s->F[0], s->F[1], s->G, s->M,
+        h_off_b[nnew] = new_rows;
+        SRV_TRY(hipMemcpyAsync(s->desc, h_desc, sizeof(SrvNew) * nnew, hipMemcpyHostToDevice, cs));
+        SRV_TRY(hipMemcpyAsync(s->srcs, h_srcs, sizeof(void *) * 2 * nnew, hipMemcpyHostToDevice, cs));
+        SRV_TRY(hipMemcpyAsync(s->chunks, h_chunks, sizeof(PlaceChunk) * nchunks, hipMemcpyHostToDevice, cs));
+        SRV_TRY(hipMemcpyAsync(s->off_b, h_off_b, sizeof(int) * (nnew + 1), hipMemcpyHostToDevice, cs));
+        launch_srv_place(cs, nchunks, s->chunks, s->desc, s->srcs, s->rp, s->col, s->F[0], s->F[1], s->G, s->M,
                          s->vbase, s->lastk);
-        launch_srv_tiles(st, nnew, new_rows, s->desc, s->off_b, s->rp, s->tiles);
+        launch_srv_tiles(cs, nnew, new_rows, s->desc, s->off_b, s->rp, s->tiles);
         SRV_TRY(hipGetLastError());
+        SRV_TRY(hipEventRecord(s->ev_placed[par], cs));
+        SRV_TRY(hipEventRecord(s->ev_dma[par], s->ds));
+        if (same_step) {
+            SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[par], 0));
+            SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[par], 0));
+            for (int k : admitted) {
+                s->slots[k].state = kRunning;
+                s->slots[k].admit_step = step;
+            }
+        } else {
+            s->staged_pending = true;
+        }
     }
 
-    // 3./4. one iteration for every resident graph
+    // 3./4. one iteration for every running graph
     int ns = 0, vhigh = 0, ndense = 0, dense_tiles = 0;
     s->flag_slot.clear();
     for (int i = 0; i < s->S; ++i) {
@@ -518,6 +611,7 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         s->done.push_back(sl.ticket);
         s->st.completed++;
         sl = Slot{};
+        s->free_slots.push_back(retired[j]);
     }
     for (int j = 0; j < ns; ++j) {
         Slot &sl = s->slots[s->flag_slot[j]];

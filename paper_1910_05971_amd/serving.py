@@ -38,6 +38,10 @@ def _bind(lib):
     lib.fastsv_server_destroy.argtypes = [vp]
     lib.fastsv_server_submit.restype = ctypes.c_int
     lib.fastsv_server_submit.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.POINTER(u64)]
+    lib.fastsv_server_submit_mapped.restype = ctypes.c_int
+    lib.fastsv_server_submit_mapped.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.POINTER(u64)]
+    lib.fastsv_server_submit_batch.restype = ctypes.c_int
+    lib.fastsv_server_submit_batch.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(i32)]
     lib.fastsv_server_step.restype = ctypes.c_int
     lib.fastsv_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fastsv_server_poll.restype = ctypes.c_int
@@ -69,21 +73,53 @@ class Server:
         self.h = h
         self.pending = {}  # ticket -> (labels, iters, rp, col) kept alive until done
 
-    def submit(self, row_ptr: np.ndarray, col: np.ndarray) -> int:
+    def submit(self, row_ptr: np.ndarray, col: np.ndarray, mapped: bool = False) -> int:
+        """mapped=True: row_ptr and col are page-locked arrays from pin_graphs
+        (fastsv_server_submit_mapped)."""
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         cl = np.ascontiguousarray(col, dtype=np.int32)
         n = rp.shape[0] - 1
         labels = np.empty(max(n, 1), dtype=np.int32)
         iters = np.zeros(1, dtype=np.int32)
         t = ctypes.c_uint64()
-        st = self.lib.fastsv_server_submit(self.h, n, int(cl.shape[0]), ctypes.c_void_p(rp.ctypes.data),
-                                           ctypes.c_void_p(cl.ctypes.data), ctypes.c_void_p(labels.ctypes.data),
-                                           ctypes.c_void_p(iters.ctypes.data), ctypes.byref(t))
+        fn = self.lib.fastsv_server_submit_mapped if mapped else self.lib.fastsv_server_submit
+        st = fn(self.h, n, int(cl.shape[0]), ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(cl.ctypes.data),
+                ctypes.c_void_p(labels.ctypes.data), ctypes.c_void_p(iters.ctypes.data), ctypes.byref(t))
         if st != B.FASTSV_OK:
             raise B.FastSVError(st, "fastsv_server_submit")
         # the server reads rp/col at admission: keep them alive until done
         self.pending[t.value] = (labels[:n], iters, rp, cl)
         return t.value
+
+    def submit_many(self, graphs, mapped: bool = False) -> list[int]:
+        """Submit many requests in one library call (fastsv_server_submit_batch);
+        graphs are objects with row_ptr and col (int32, contiguous).  Returns
+        the tickets in order."""
+        k = len(graphs)
+        if k == 0:
+            return []
+        rps = [np.ascontiguousarray(g.row_ptr, dtype=np.int32) for g in graphs]
+        cols = [np.ascontiguousarray(g.col, dtype=np.int32) for g in graphs]
+        n = np.array([r.shape[0] - 1 for r in rps], dtype=np.int32)
+        nnz = np.array([c.shape[0] for c in cols], dtype=np.int64)
+        labels = np.empty(int(np.maximum(n, 1).sum()), dtype=np.int32)
+        lab_off = np.concatenate([[0], np.cumsum(np.maximum(n, 1))[:-1]]).astype(np.int64)
+        iters = np.zeros(k, dtype=np.int32)
+        rp_p = np.array([r.ctypes.data for r in rps], dtype=np.uint64)
+        col_p = np.array([c.ctypes.data for c in cols], dtype=np.uint64)
+        lab_p = (labels.ctypes.data + 4 * lab_off).astype(np.uint64)
+        tickets = np.zeros(k, dtype=np.uint64)
+        acc = ctypes.c_int32()
+        st = self.lib.fastsv_server_submit_batch(
+            self.h, k, ctypes.c_void_p(n.ctypes.data), ctypes.c_void_p(nnz.ctypes.data),
+            ctypes.c_void_p(rp_p.ctypes.data), ctypes.c_void_p(col_p.ctypes.data), ctypes.c_void_p(lab_p.ctypes.data),
+            ctypes.c_void_p(iters.ctypes.data), ctypes.c_void_p(tickets.ctypes.data), int(bool(mapped)),
+            ctypes.byref(acc))
+        for i in range(acc.value):
+            self.pending[int(tickets[i])] = (labels[lab_off[i]:lab_off[i] + n[i]], iters[i:i + 1], rps[i], cols[i])
+        if st != B.FASTSV_OK:
+            raise B.FastSVError(st, "fastsv_server_submit_batch")
+        return [int(t) for t in tickets]
 
     def step(self):
         r, q = ctypes.c_int32(), ctypes.c_int32()
@@ -124,7 +160,7 @@ class Server:
             pass
 
 
-def run_open_loop(server: Server, graphs, arrivals, on_done=None, idle_sleep=0.0):
+def run_open_loop(server: Server, graphs, arrivals, on_done=None, idle_sleep=0.0, mapped=False):
     """Replay requests graphs[i] (objects with row_ptr/col) arriving at
     arrivals[i] seconds after the start.  Returns (latency seconds per request,
     makespan seconds, iterations per request)."""
@@ -137,11 +173,17 @@ def run_open_loop(server: Server, graphs, arrivals, on_done=None, idle_sleep=0.0
     outstanding = 0
     while nxt < len(order) or outstanding:
         now = time.perf_counter() - t0
+        arrived = []
         while nxt < len(order) and arrivals[order[nxt]] <= now:
-            i = int(order[nxt])
-            ticket_of[server.submit(graphs[i].row_ptr, graphs[i].col)] = i
+            arrived.append(int(order[nxt]))
             nxt += 1
-            outstanding += 1
+        if len(arrived) == 1:
+            i = arrived[0]
+            ticket_of[server.submit(graphs[i].row_ptr, graphs[i].col, mapped=mapped)] = i
+        elif arrived:
+            for i, t in zip(arrived, server.submit_many([graphs[i] for i in arrived], mapped=mapped)):
+                ticket_of[t] = i
+        outstanding += len(arrived)
         if outstanding:
             server.step()
             for t, lab, its in server.poll():

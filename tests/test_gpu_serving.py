@@ -14,8 +14,9 @@ pytestmark = pytest.mark.gpu
 
 
 def _mix():
+    # rmat(18, 16) has more than 2^22 entries: its column ids go by DMA
     gs = [gg.er(3000, 5000, seed=61), gg.er(20000, 100000, seed=62), gg.rmat(13, 8, seed=63),
-          gg.grid(60, 70, 0.55, seed=64), gg.er(64, 100, seed=65)]
+          gg.grid(60, 70, 0.55, seed=64), gg.er(64, 100, seed=65), gg.rmat(18, 16, seed=66)]
     rp, col = P.csr_from_pairs(1, [])
     gs.append(gg.Graph("single", 1, rp, col, 0))
     rp, col = P.csr_from_pairs(50, [])
@@ -38,7 +39,7 @@ def test_server_matches_solo(gpu_ok, tau):
     from paper_1910_05971_amd.serving import Server
     gs = _mix()
     want = [_expected(g) for g in gs]
-    srv = Server(max_vertices=200_000, max_entries=2_000_000, max_slots=16, frontier_tau=tau)
+    srv = Server(max_vertices=600_000, max_entries=12_000_000, max_slots=16, frontier_tau=tau)
     ticket_of = {}
     got = {}
     rng = np.random.default_rng(1)
@@ -97,12 +98,15 @@ def test_server_rejects(gpu_ok):
 
 
 
-def test_server_page_locked_requests(gpu_ok):
-    # page-locked request arrays are read by the placement kernel directly
+@pytest.mark.parametrize("mapped", [False, True])
+def test_server_page_locked_requests(gpu_ok, mapped):
+    # page-locked request arrays: small ones read by the placement kernel in
+    # place, large ones copied by DMA; admissions after the first step are
+    # placed on the copy stream while the resident graphs iterate
     from paper_1910_05971_amd.serving import Server, pin_graphs
     gs = pin_graphs(_mix())
-    srv = Server(max_vertices=200_000, max_entries=2_000_000, max_slots=8, validate=False)
-    tickets = {srv.submit(g.row_ptr, g.col): i for i, g in enumerate(gs)}
+    srv = Server(max_vertices=600_000, max_entries=12_000_000, max_slots=8, validate=False)
+    tickets = {srv.submit(g.row_ptr, g.col, mapped=mapped): i for i, g in enumerate(gs)}
     got = {}
     for _ in range(10000):
         r, q = srv.step()
@@ -115,3 +119,28 @@ def test_server_page_locked_requests(gpu_ok):
         lab, its = _expected(g)
         assert np.array_equal(got[i][0], lab), g.name
         assert got[i][1] == its, g.name
+
+
+@pytest.mark.parametrize("mapped", [False, True])
+def test_server_batch_submit(gpu_ok, mapped):
+    # all requests in one call; a pool that holds only part of them at a time
+    from paper_1910_05971_amd.serving import Server, pin_graphs
+    gs = _mix()
+    if mapped:
+        gs = pin_graphs(gs)
+    want = [_expected(g) for g in gs]
+    srv = Server(max_vertices=300_000, max_entries=9_000_000, max_slots=6, validate=not mapped)
+    tickets = srv.submit_many(gs, mapped=mapped)
+    assert len(set(tickets)) == len(gs)
+    of = {t: i for i, t in enumerate(tickets)}
+    got = {}
+    for _ in range(10000):
+        srv.step()
+        for t, lab, its in srv.poll():
+            got[of[t]] = (lab.copy(), its)
+        if len(got) == len(gs):
+            break
+    srv.close()
+    for i, g in enumerate(gs):
+        assert np.array_equal(got[i][0], want[i][0]), g.name
+        assert got[i][1] == want[i][1], (g.name, got[i][1], want[i][1])
