@@ -14,10 +14,10 @@
 // stores, per entry of bin b, the source v (int32) and the row offset u - bW
 // (uint16), bin after bin.  A dense iteration then runs one workgroup per
 // bin: it streams the bin's entries, gathers G[v] in ascending order of v,
-// and min-reduces into an LDS window of W rows.  The sweep is cut into source
-// ranges, one launch each, so that all workgroups gather from the same slice
-// of G at the same time and share its lines in L2.  Rows are then finished as
-// in the pull pass (M update, aggressive and stochastic hooks).
+// and min-reduces into an LDS window of W rows.  The waves of a workgroup
+// advance through the bin in step, so that they gather from the same narrow
+// slice of G at the same time and share its lines in L1 and L2.  Rows are then
+// finished as in the pull pass (M update, aggressive and stochastic hooks).
 // The minimum is order-free, so the iterate is bit-identical to the pull
 // pass's.
 //
@@ -240,19 +240,19 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict
     }
 }
 
-// Dense pass over the binned layout, source range r of nrange: one
-// workgroup per bin, the bin's W rows in LDS.  All bins are cut at the same
-// chunk boundaries, so the workgroups of one launch gather from the same
-// slice of G and share its lines in L2; the launches of one iteration run
-// the ranges in order.  Between launches a bin's partial minima are parked in
-// wbuf (W ints per bin): range 0 starts from INT_MAX, the last range finishes
-// the rows as the pull pass does (M update, aggressive and stochastic hooks).
-__global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks, int r, int nrange,
-                                                   const int *__restrict__ off, const int *__restrict__ bsrc,
+// Dense pass over the binned layout: one workgroup per bin, the bin's W rows
+// in LDS from the first entry to the last, then the rows are finished as in
+// the pull pass (M update, aggressive and stochastic hooks).  The bin's
+// entries are sorted by source, and the workgroup walks them in block-wide
+// steps of kWaves * kSpan consecutive entries with a barrier after each, so
+// that its waves gather from the same narrow slice of G at the same time and
+// share its lines in L1 and L2.  All bins are launched at once; the device
+// starts later bins as earlier ones finish.
+__global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks, const int *__restrict__ off,
+                                                   const int *__restrict__ bsrc,
                                                    const unsigned short *__restrict__ bdst,
-                                                   int *__restrict__ wbuf, const int *__restrict__ F,
-                                                   int *__restrict__ Fn, const int *__restrict__ G,
-                                                   int *__restrict__ M) {
+                                                   const int *__restrict__ F, int *__restrict__ Fn,
+                                                   const int *__restrict__ G, int *__restrict__ M) {
     __shared__ int wmin[1 << kBinShiftMax];
     constexpr int kSpan = kWave * kBinSpan;
     constexpr int kWaves = 1024 / kWave;
@@ -261,16 +261,12 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks
     const int b = blockIdx.x;
     const int u0 = b << shift;
     const int rows = min(1 << shift, n - u0);
-    int *park = wbuf + ((int64_t)b << shift);
-    if (r == 0) {
-        for (int i = tid; i < rows; i += 1024) wmin[i] = INT_MAX;
-    } else {
-        for (int i = tid; i < rows; i += 1024) wmin[i] = __builtin_nontemporal_load(park + i);
-    }
+    for (int i = tid; i < rows; i += 1024) wmin[i] = INT_MAX;
+    const int p0 = off[(int64_t)b * nchunks], p1 = off[(int64_t)(b + 1) * nchunks];
     __syncthreads();
-    const int c0 = (int)((int64_t)nchunks * r / nrange), c1 = (int)((int64_t)nchunks * (r + 1) / nrange);
-    const int p1 = off[(int64_t)b * nchunks + c1];
-    for (int base = off[(int64_t)b * nchunks + c0] + wave * kSpan; base < p1; base += kWaves * kSpan) {
+    // the trip count is the same for every wave: the barrier is reached by all
+    for (int blk = p0; blk < p1; blk += kWaves * kSpan) {
+        const int base = blk + wave * kSpan;
         int v[kBinSpan], d[kBinSpan];
         if (base + kSpan <= p1) {
 #pragma unroll
@@ -282,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks
             for (int x = 0; x < kBinSpan; ++x) v[x] = G[v[x]];
 #pragma unroll
             for (int x = 0; x < kBinSpan; ++x) atomicMin(&wmin[d[x]], v[x]);
-        } else {
+        } else if (base < p1) {
 #pragma unroll
             for (int x = 0; x < kBinSpan; ++x) {
                 const int p = min(base + x * kWave + lane, p1 - 1);
@@ -295,11 +291,7 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks
             for (int x = 0; x < kBinSpan; ++x)
                 if (base + x * kWave + lane < p1) atomicMin(&wmin[d[x]], v[x]);
         }
-    }
-    __syncthreads();
-    if (r + 1 < nrange) {
-        for (int i = tid; i < rows; i += 1024) __builtin_nontemporal_store(wmin[i], park + i);
-        return;
+        __syncthreads();
     }
     for (int i = tid; i < rows; i += 1024) {
         const int m = wmin[i];

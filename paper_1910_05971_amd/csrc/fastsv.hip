@@ -61,11 +61,11 @@ struct Layout {
     int cb_shift, nblk;
     int64_t scan_len, scan_sums;
     bool bin;        // binned dense pass arrays present
-    int bin_shift, nbins, bin_ranges, nchunks, chunk_tiles;
+    int bin_shift, nbins, nchunks, chunk_tiles;
     int64_t bin_scan_len;
     size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_tiles, off_ctr;
     size_t off_cbcol, off_segptr, off_segrow, off_cnte, off_cnts, off_sums_e, off_sums_s, off_cbtiles, off_info;
-    size_t off_bsrc, off_bdst, off_bcnt, off_bsums, off_wbuf;
+    size_t off_bsrc, off_bdst, off_bcnt, off_bsums;
     size_t total;
 };
 
@@ -151,16 +151,10 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
         L.chunk_tiles = (int)ct;
         L.nchunks = (int)((L.ntiles + ct - 1) / ct);
         L.bin_scan_len = nb * L.nchunks + 1;
-        // source ranges of the dense pass (one launch each): 2^(bsh + kBinRangeRowsLog) rows
-        const int rl = bsh + kBinRangeRowsLog;
-        int64_t nr = (n + ((int64_t)1 << rl) - 1) >> rl;
-        if (nr > L.nchunks) nr = L.nchunks;
-        L.bin_ranges = (int)nr;
         L.off_bsrc = take(sizeof(int) * (size_t)nnz);
         L.off_bdst = take(sizeof(unsigned short) * (size_t)nnz);
         L.off_bcnt = take(sizeof(int) * (size_t)L.bin_scan_len);
         L.off_bsums = take(sizeof(int) * (size_t)(grid_for(L.bin_scan_len, kScanBlock) + 1));
-        L.off_wbuf = nr > 1 ? take(sizeof(int) * (size_t)(nb << bsh)) : 0;
     }
     L.total = p;
     return L;
@@ -179,7 +173,6 @@ struct Workspace {
     int *bsrc;
     unsigned short *bdst;
     int *bcnt, *bsums;
-    int *wbuf;
 };
 
 Workspace carve(void *base, const Layout &L) {
@@ -208,7 +201,6 @@ Workspace carve(void *base, const Layout &L) {
         w.bdst = reinterpret_cast<unsigned short *>(p + L.off_bdst);
         w.bcnt = reinterpret_cast<int *>(p + L.off_bcnt);
         w.bsums = reinterpret_cast<int *>(p + L.off_bsums);
-        w.wbuf = L.bin_ranges > 1 ? reinterpret_cast<int *>(p + L.off_wbuf) : nullptr;
     }
     return w;
 }
@@ -715,9 +707,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
                 if (stats) stats->blocked_iterations++;
             } else if (bin_state == 1) {
-                for (int r = 0; r < L.bin_ranges; ++r)
-                    hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bin_shift, L.nchunks, r,
-                                       L.bin_ranges, w.bcnt, w.bsrc, w.bdst, w.wbuf, F, Fn, G, w.M);
+                hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bin_shift, L.nchunks, w.bcnt,
+                                   w.bsrc, w.bdst, F, Fn, G, w.M);
                 if (stats) stats->binned_iterations++;
             } else {
                 launch_dense(stream, base ? kDenseBaseGather : kDenseGather, w.tiles, (int)ntiles, P.rp, P.col,
