@@ -112,9 +112,10 @@ typedef struct {
     int32_t blocked_iterations;    /* dense iterations that ran the column-blocked passes */
     int32_t binned_iterations;     /* dense iterations that ran the binned passes */
     int32_t num_bins;              /* bins of the binned layout (0 when it was not built) */
-    int32_t bin_fused_first;       /* 1 if the layout was built by the first iteration's pass
-                                      (its time is then ms_hook[0]) */
-    float ms_bin_prepare;          /* time to build the binned layout separately (opts.timing) */
+    int32_t bin_fused_first;       /* 1 if the layout's fill pass also performed the first
+                                      iteration (that pass is then ms_hook[0]) */
+    float ms_bin_prepare;          /* time to build the binned layout; with bin_fused_first only
+                                      its count and scan before the fill (opts.timing) */
     int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */
     int64_t alg_bytes;             /* algorithmic bytes of all executed iterations (4 B per int32
                                       read or written, each gather counted) */

@@ -241,10 +241,11 @@ void cb_prepare(const Layout &L, const Workspace &w, const int *rp, const int *c
 // also performs the first iteration's hooking (the grandparent vector is then
 // still the identity).
 void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream,
-                 int *M = nullptr, int *Fn = nullptr) {
+                 int *M = nullptr, int *Fn = nullptr, hipEvent_t before_fill = nullptr) {
     hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, L.bin_shift,
                        L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
     scan_inplace(w.bcnt, L.bin_scan_len, w.bsums, stream);
+    if (before_fill) (void)hipEventRecord(before_fill, stream);
     const size_t lds = 3 * sizeof(int) * (size_t)L.nbins;
     if (M)
         hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kBinThreads), lds, stream, w.tiles, (int)L.ntiles,
@@ -381,7 +382,7 @@ struct fastsv_ctx {
     Counters *host_ctr = nullptr;  // pinned
     void *ws = nullptr;
     size_t ws_size = 0;
-    hipEvent_t ev[3] = {};
+    hipEvent_t ev[4] = {};
     bool events = false;
 };
 
@@ -686,7 +687,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             alg += 16 * prev_fcnt + 12 * prev_edges;
         } else {
             if (it == 1 && fuse_first) {
-                bin_prepare(L, w, n, P.rp, P.col, stream, w.M, Fn);
+                bin_prepare(L, w, n, P.rp, P.col, stream, w.M, Fn, timed ? ctx->ev[3] : nullptr);
                 bin_state = 1;
                 if (stats) {
                     stats->num_bins = L.nbins;
@@ -737,6 +738,13 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 float a = 0, b = 0;
                 HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
                 HIP_TRY(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
+                if (it == 1 && fuse_first) {
+                    // the count and scan before the fill, and the fill itself
+                    float c = 0;
+                    HIP_TRY(hipEventElapsedTime(&c, ctx->ev[0], ctx->ev[3]));
+                    stats->ms_bin_prepare = c;
+                    a -= c;
+                }
                 stats->ms_hook[ti] = a;
                 stats->ms_gp[ti] = b;
             }

@@ -3,7 +3,7 @@
 // Resident graphs share one device pool and advance together: every step is
 // one iteration of Algorithm 3 (dense pull over the resident graphs' tiles or
 // sparse push over the frontier, then the grandparent pass) for all of them.
-// A graph admitted at step s runs its first iteration in step s; it retires
+// A graph starts with the step after its placement (see 2. below); it retires
 // after the first step in which none of its grandparents changed (the
 // termination test of Sec. 3.4 applied to that graph alone).  Ids in f and gf
 // are pool-global, so resident graphs never exchange values and each one
@@ -12,11 +12,19 @@
 // Admission is first-come first-served and by footprint: a request waits
 // until a slot, n+1 pool vertices and nnz pool entries are free.
 //
-// One step, all on the server's stream with a single host synchronisation:
+// One step: the iteration runs on the server's stream with a single host
+// synchronisation, and admission runs beside it on two copy streams:
+//   0. graphs placed by the previous step join the running set (the stream
+//      waits for their placement); vertex, entry and tile ranges retired by
+//      the previous step return to their allocators
 //   1. graphs found converged by the previous step: labels out to staging,
 //      vertex range back to the neutral state (one launch for all of them)
-//   2. admission: the staged CSRs of the admitted graphs are copied once and
-//      placed into the pool by one launch; their tiles are built
+//   2. admission of up to about kSrvStepAdmitBytes of requests: one placement
+//      launch on the copy stream reads the row pointers and small column
+//      arrays in place from page-locked host memory (pageable ones are staged
+//      by DMA first), large or pageable column arrays go by DMA on the second
+//      copy stream, and the tiles are built.  The admitted graphs run from the
+//      next step on, or from this one when nothing else is resident.
 //   3. hooking, decided per graph: the dense pull over the graph's resident
 //      tiles in its first iteration and whenever its frontier (total degree of
 //      the grandparents that changed in the previous step) exceeds
