@@ -72,8 +72,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
     if (k == 0 && tid == 0) cnt[(int64_t)nbins * nchunks] = 0;  // becomes the total after the scan
 }
 
-// Fill pass: one workgroup per chunk, processed kBinThreads / kWave tiles at a
-// time (one tile per wave).  Each round sorts its entries by bin in LDS and
+// Fill pass: one workgroup per chunk, processed kFillThreads / kWave tiles at
+// a time (one tile per wave).  Each round sorts its entries by bin in LDS and
 // writes every bin's run at the bin's cursor, which starts at the chunk's
 // offset from the scan: a (chunk, bin) run belongs to this workgroup only.
 // With kFirst the pass also performs the first iteration of the method, whose
@@ -82,33 +82,33 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
 // since f is the identity too); it replaces the first pull pass.
 // Dynamic LDS: 3 * nbins ints.
 template <bool kFirst>
-__global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
+__global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
                                                           const int *__restrict__ rp, const int *__restrict__ col,
                                                           int shift, int nbins, int nchunks, int chunk_tiles,
                                                           const int *__restrict__ off, int *__restrict__ bsrc,
                                                           unsigned short *__restrict__ bdst, int *__restrict__ M,
                                                           int *__restrict__ Fn) {
-    constexpr int kWaves = kBinThreads / kWave;
-    static_assert(kWaves * kRowWin <= kWaves * kTileEntries, "row minima share the staging array");
+    constexpr int kWaves = kFillThreads / kWave;
+    static_assert(kRowWin <= kTileEntries, "row windows and row minima share the staging arrays");
     extern __shared__ int s_dyn[];
     int *cur = s_dyn;               // next free position of the bin's run
     int *hist = s_dyn + nbins;      // round's count per bin
     int *loff = s_dyn + 2 * nbins;  // round's exclusive offset per bin in the stage
-    __shared__ int win[kWaves][kRowWin];
     __shared__ int sv[kWaves * kTileEntries];  // staged sources
     __shared__ int su[kWaves * kTileEntries];  // staged columns
     __shared__ int s_wsum[kWaves];
-    // first iteration: per-row minima of the wave's tile; they live from the
-    // round's first barrier to its second, the staged sources from its fourth
-    // to its sixth, so they share memory
+    // the wave's window of row starts and (first iteration) its per-row minima
+    // live from the round's start to its third barrier, the staged entries
+    // from its fourth to its sixth, so they share memory
+    int *winw = su + (threadIdx.x / kWave) * kRowWin;
     int *rminw = sv + (threadIdx.x / kWave) * kRowWin;
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = lane_id();
     const int k = xcd_major(blockIdx.x, gridDim.x);
-    for (int b = tid; b < nbins; b += kBinThreads) cur[b] = off[(int64_t)b * nchunks + k];
+    for (int b = tid; b < nbins; b += kFillThreads) cur[b] = off[(int64_t)b * nchunks + k];
     const int mask = (1 << shift) - 1;
-    const int per = (nbins + kBinThreads - 1) / kBinThreads;
+    const int per = (nbins + kFillThreads - 1) / kFillThreads;
     const int b0 = tid * per, b1 = min(b0 + per, nbins);
     for (int b = b0; b < b1; ++b) hist[b] = 0;
     for (int t0 = k * chunk_tiles; t0 < min((k + 1) * chunk_tiles, ntiles); t0 += kWaves) {
@@ -134,11 +134,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict
         const bool in_lds = tile_ok && nwin <= kRowWin;
         if (in_lds)
             for (int j = lane; j < nwin; j += kWave) {
-                win[wave][j] = rp[T.r_lo + j];
+                winw[j] = rp[T.r_lo + j];
                 if (kFirst) rminw[j] = INT_MAX;
             }
         __syncthreads();
-        const int *wrow = &win[wave][0];
+        const int *wrow = winw;
         auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
         // source row of every entry and its rank inside its bin in this round
         int row = T.r_lo, nxt = 0;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_fill(const Tile *__restrict
             }
         }
         __syncthreads();
-        for (int sidx = tid; sidx < total; sidx += kBinThreads) {
+        for (int sidx = tid; sidx < total; sidx += kFillThreads) {
             const int u = su[sidx];
             const int b = u >> shift;
             const int pos = cur[b] + (sidx - loff[b]);

@@ -60,9 +60,10 @@ constexpr int kMaxBins = 2048;          // bins per graph (scatter histogram in 
 constexpr int kBinShiftMax = 15;        // 2^15 rows = 128 KB LDS window in the apply pass
 constexpr int kBinShiftMin = 8;
 constexpr int kBinSpan = 16;            // entries per lane and step of the binned dense pass
-constexpr int kBinThreads = 256;        // layout build: one tile per wave and round
+constexpr int kBinThreads = 256;        // layout count pass
+constexpr int kFillThreads = 512;       // layout fill: one tile per wave and round
 constexpr int64_t kBinMaxCounts = 1 << 27;  // (bin, chunk) counters of the layout build
-constexpr int kBinChunkTilesMin = 32;   // tiles per chunk of the layout build (8 rounds of 4)
+constexpr int kBinChunkTilesMin = 32;   // tiles per chunk of the layout build (whole fill rounds)
 constexpr int kNumXcd = 8;              // workgroups are dealt round-robin to the XCDs
 
 // Workgroup index -> work index such that the workgroups on one XCD (index

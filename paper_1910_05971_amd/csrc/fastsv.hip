@@ -145,8 +145,8 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
         L.nbins = (int)nb;
         // chunks of whole rounds of tiles: at least kBinChunkTilesMin tiles, so that a
         // (chunk, bin) run spans whole cache lines, and few enough for the counter budget
-        const int64_t rounds = (L.ntiles + kBinThreads / kWave - 1) / (kBinThreads / kWave);
-        int64_t ct = (kBinThreads / kWave) * ((nb * rounds + kBinMaxCounts - 1) / kBinMaxCounts);
+        const int64_t rounds = (L.ntiles + kFillThreads / kWave - 1) / (kFillThreads / kWave);
+        int64_t ct = (kFillThreads / kWave) * ((nb * rounds + kBinMaxCounts - 1) / kBinMaxCounts);
         if (ct < kBinChunkTilesMin) ct = kBinChunkTilesMin;
         L.chunk_tiles = (int)ct;
         L.nchunks = (int)((L.ntiles + ct - 1) / ct);
@@ -248,10 +248,10 @@ void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, cons
     if (before_fill) (void)hipEventRecord(before_fill, stream);
     const size_t lds = 3 * sizeof(int) * (size_t)L.nbins;
     if (M)
-        hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kBinThreads), lds, stream, w.tiles, (int)L.ntiles,
+        hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
                            n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst, M, Fn);
     else
-        hipLaunchKernelGGL(k_bin_fill<false>, dim3(L.nchunks), dim3(kBinThreads), lds, stream, w.tiles, (int)L.ntiles,
+        hipLaunchKernelGGL(k_bin_fill<false>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
                            n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst,
                            nullptr, nullptr);
 }
