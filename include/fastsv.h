@@ -76,12 +76,14 @@ typedef struct {
                                widened so that there are at most 64 blocks).  4..30 otherwise, and
                                the graph must then have at most 64 blocks. */
     int32_t binned;         /* binned dense SpMV: the stored entries are regrouped once per call
-                               by 2^bin_shift-row bins of their column (6 B per entry), and each
-                               dense iteration from the second on reduces a bin in LDS while
+                               by bins of consecutive vertices of their column (6 B per entry), and
+                               each dense iteration from the second on reduces a bin in LDS while
                                gathering gf in ascending order.  1 use it, 0 never, -1 automatic
                                (the default: graphs with more than 2^22 vertices).  Same iterates
                                either way; not used when the graph needs more than 2048 bins. */
-    int32_t bin_shift;      /* log2 of the bin width in vertices; 0 = automatic (15); 8..15 */
+    int32_t bin_shift;      /* bin width 2^bin_shift vertices, 8..15; 0 = automatic: the fewest
+                               bins that are a multiple of 256 (the CU count) with at most 40960
+                               vertices each (the dense pass's 160 KB LDS window) */
     int32_t sv_flags;       /* convergence ablation (Sec. 5.2): which of the four changes of Sec. 3
                                that turn Algorithm 1 into Algorithm 2 are applied.  Bit 1 grandparent
                                hooking (Sec. 3.1), 2 stochastic hooking (3.2), 4 aggressive hooking

@@ -7,7 +7,8 @@
 // 4-byte value costs a whole cache line from the fabric.
 //
 // Here the stored entries are regrouped once per solve.  Rows are cut into
-// bins of W = 2^S consecutive vertices.  Because the CSR is symmetric, the
+// bins of W consecutive vertices (at most 40960, the most whose minima fit
+// the 160 KB of LDS).  Because the CSR is symmetric, the
 // entries (u, v) with u in bin b are exactly the entries (v, u) of the CSR
 // whose column u falls in bin b; listing those in the CSR's own storage order
 // (rows v ascending) gives bin b's entries sorted by source v.  The layout
@@ -43,7 +44,7 @@ namespace fsv {
 // from k * chunk_tiles * kTileEntries on.  Entries with a column id outside
 // [0, n) are not counted (and not placed by the fill pass).
 __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, const int *__restrict__ col,
-                                                           int shift, int nbins, int nchunks, int chunk_tiles,
+                                                           BinDiv bd, int nbins, int nchunks, int chunk_tiles,
                                                            int *__restrict__ cnt) {
     __shared__ int hist[kMaxBins];
     const int tid = threadIdx.x;
@@ -56,14 +57,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
     for (int64_t e = e0 + 4 * tid; e < e1; e += 4 * kBinThreads) {
         if (vec && e + 4 <= e1) {
             const v4i c = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + e));
-            if (c.x >= 0 && c.x < n) atomicAdd(&hist[c.x >> shift], 1);
-            if (c.y >= 0 && c.y < n) atomicAdd(&hist[c.y >> shift], 1);
-            if (c.z >= 0 && c.z < n) atomicAdd(&hist[c.z >> shift], 1);
-            if (c.w >= 0 && c.w < n) atomicAdd(&hist[c.w >> shift], 1);
+            if (c.x >= 0 && c.x < n) atomicAdd(&hist[bin_of(c.x, bd)], 1);
+            if (c.y >= 0 && c.y < n) atomicAdd(&hist[bin_of(c.y, bd)], 1);
+            if (c.z >= 0 && c.z < n) atomicAdd(&hist[bin_of(c.z, bd)], 1);
+            if (c.w >= 0 && c.w < n) atomicAdd(&hist[bin_of(c.w, bd)], 1);
         } else {
             for (int64_t f = e; f < min(e + 4, e1); ++f) {
                 const int c = col[f];
-                if (c >= 0 && c < n) atomicAdd(&hist[c >> shift], 1);
+                if (c >= 0 && c < n) atomicAdd(&hist[bin_of(c, bd)], 1);
             }
         }
     }
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
 template <bool kFirst>
 __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
                                                           const int *__restrict__ rp, const int *__restrict__ col,
-                                                          int shift, int nbins, int nchunks, int chunk_tiles,
+                                                          BinDiv bd, int nbins, int nchunks, int chunk_tiles,
                                                           const int *__restrict__ off, int *__restrict__ bsrc,
                                                           unsigned short *__restrict__ bdst, int *__restrict__ M,
                                                           int *__restrict__ Fn) {
@@ -107,7 +108,6 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
     const int lane = lane_id();
     const int k = xcd_major(blockIdx.x, gridDim.x);
     for (int b = tid; b < nbins; b += kFillThreads) cur[b] = off[(int64_t)b * nchunks + k];
-    const int mask = (1 << shift) - 1;
     const int per = (nbins + kFillThreads - 1) / kFillThreads;
     const int b0 = tid * per, b1 = min(b0 + per, nbins);
     for (int b = b0; b < b1; ++b) hist[b] = 0;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
             const bool ok = j < cnt && c[j] >= 0 && c[j] < n;
-            rank[j] = ok ? atomicAdd(&hist[c[j] >> shift], 1) : -1;
+            rank[j] = ok ? atomicAdd(&hist[bin_of(c[j], bd)], 1) : -1;
         }
         if (kFirst && cnt > 0) {
             // minimum column of every row segment of the lane: into the tile's
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
             if (rank[j] >= 0) {
-                const int sidx = loff[c[j] >> shift] + rank[j];
+                const int sidx = loff[bin_of(c[j], bd)] + rank[j];
                 sv[sidx] = r[j];
                 su[sidx] = c[j];
             }
@@ -226,10 +226,10 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
         __syncthreads();
         for (int sidx = tid; sidx < total; sidx += kFillThreads) {
             const int u = su[sidx];
-            const int b = u >> shift;
+            const int b = bin_of(u, bd);
             const int pos = cur[b] + (sidx - loff[b]);
             bsrc[pos] = sv[sidx];
-            bdst[pos] = (unsigned short)(u & mask);
+            bdst[pos] = (unsigned short)(u - b * bd.rows);
         }
         __syncthreads();
         for (int b = b0; b < b1; ++b) {
@@ -248,19 +248,19 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
 // that its waves gather from the same narrow slice of G at the same time and
 // share its lines in L1 and L2.  All bins are launched at once; the device
 // starts later bins as earlier ones finish.
-__global__ __launch_bounds__(1024) void k_bin_pull(int n, int shift, int nchunks, const int *__restrict__ off,
+__global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, const int *__restrict__ off,
                                                    const int *__restrict__ bsrc,
                                                    const unsigned short *__restrict__ bdst,
                                                    const int *__restrict__ F, int *__restrict__ Fn,
                                                    const int *__restrict__ G, int *__restrict__ M) {
-    __shared__ int wmin[1 << kBinShiftMax];
+    __shared__ int wmin[kBinRowsMax];
     constexpr int kSpan = kWave * kBinSpan;
     constexpr int kWaves = 1024 / kWave;
     const int tid = threadIdx.x;
     const int lane = lane_id(), wave = tid / kWave;
     const int b = blockIdx.x;
-    const int u0 = b << shift;
-    const int rows = min(1 << shift, n - u0);
+    const int u0 = b * W;
+    const int rows = min(W, n - u0);
     for (int i = tid; i < rows; i += 1024) wmin[i] = INT_MAX;
     const int p0 = off[(int64_t)b * nchunks], p1 = off[(int64_t)(b + 1) * nchunks];
     __syncthreads();

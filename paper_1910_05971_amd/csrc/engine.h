@@ -34,6 +34,31 @@ struct Tile {
     int r_lo, r_hi;  // rows containing entries e0 and e1-1
 };
 
+// Bin of a vertex id for a bin width W that need not be a power of two:
+// floor(u / W) = (u * m) >> s with s = 31 + ceil(log2 W) and m = ceil(2^s / W).
+// With m = (2^s + e) / W, 0 <= e < W, the product overshoots u / W by
+// u * e / (W * 2^s) < 2^31 / 2^s <= 1 / W, which never reaches the next
+// integer, so the quotient is exact for every 0 <= u < 2^31.
+struct BinDiv {
+    int rows;              // W
+    int s;
+    unsigned long long m;
+};
+
+inline BinDiv make_bindiv(int W) {
+    int l = 0;
+    while ((1LL << l) < W) ++l;
+    BinDiv d;
+    d.rows = W;
+    d.s = 31 + l;
+    d.m = (unsigned long long)((((unsigned __int128)1 << d.s) + (unsigned)W - 1) / (unsigned)W);
+    return d;
+}
+
+__device__ __forceinline__ int bin_of(int u, const BinDiv &d) {
+    return (int)(((unsigned long long)(unsigned)u * d.m) >> d.s);
+}
+
 // Per-iteration counters written by the grandparent pass (two slots, used
 // alternately by consecutive iterations).
 struct IterCounters {
@@ -57,8 +82,10 @@ constexpr int kModeAsync = 1;   // one f read and written concurrently
 
 // ---- binned dense pass geometry ----
 constexpr int kMaxBins = 2048;          // bins per graph (scatter histogram in LDS)
-constexpr int kBinShiftMax = 15;        // 2^15 rows = 128 KB LDS window in the apply pass
+constexpr int kBinShiftMax = 15;        // largest power-of-two bin width that may be asked for
 constexpr int kBinShiftMin = 8;
+constexpr int kBinRowsMax = 40960;      // widest bin: a 160 KB LDS window in the dense pass
+constexpr int kNumCUs = 256;            // MI355X compute units: one dense-pass workgroup each at a time
 constexpr int kBinSpan = 16;            // entries per lane and step of the binned dense pass
 constexpr int kBinThreads = 256;        // layout count pass
 constexpr int kFillThreads = 512;       // layout fill: one tile per wave and round

@@ -61,7 +61,8 @@ struct Layout {
     int cb_shift, nblk;
     int64_t scan_len, scan_sums;
     bool bin;        // binned dense pass arrays present
-    int bin_shift, nbins, nchunks, chunk_tiles;
+    BinDiv bdiv;  // bin width W and the divisor for u / W
+    int nbins, nchunks, chunk_tiles;
     int64_t bin_scan_len;
     size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_tiles, off_ctr;
     size_t off_cbcol, off_segptr, off_segrow, off_cnte, off_cnts, off_sums_e, off_sums_s, off_cbtiles, off_info;
@@ -137,11 +138,16 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
     // binned dense passes: per stored entry its source (int32) and row offset
     // in the bin (uint16), the (bin, chunk) counts and their scan, the slice
     // table of the dense pass
-    const int bsh = lo.bin_shift > 0 ? lo.bin_shift : kBinShiftMax;
-    const int64_t nb = (n + (int64_t(1) << bsh) - 1) >> bsh;
+    // automatic width: the fewest bins that are a multiple of the CU count
+    // (the dense pass then runs whole rounds of one workgroup per CU) with at
+    // most kBinRowsMax rows each
+    const int64_t nb_auto =
+        (int64_t)kNumCUs * std::max<int64_t>(1, (n + (int64_t)kNumCUs * kBinRowsMax - 1) / ((int64_t)kNumCUs * kBinRowsMax));
+    const int W = lo.bin_shift > 0 ? 1 << lo.bin_shift : (int)std::max<int64_t>(1, (n + nb_auto - 1) / nb_auto);
+    const int64_t nb = (n + W - 1) / W;
     L.bin = nnz > 0 && nb <= kMaxBins && (lo.bin_mode == 1 || (lo.bin_mode == -1 && n > kBinAutoMinN));
     if (L.bin) {
-        L.bin_shift = bsh;
+        L.bdiv = make_bindiv(W);
         L.nbins = (int)nb;
         // chunks of whole rounds of tiles: at least kBinChunkTilesMin tiles, so that a
         // (chunk, bin) run spans whole cache lines, and few enough for the counter budget
@@ -242,17 +248,17 @@ void cb_prepare(const Layout &L, const Workspace &w, const int *rp, const int *c
 // still the identity).
 void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream,
                  int *M = nullptr, int *Fn = nullptr, hipEvent_t before_fill = nullptr) {
-    hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, L.bin_shift,
+    hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, L.bdiv,
                        L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
     scan_inplace(w.bcnt, L.bin_scan_len, w.bsums, stream);
     if (before_fill) (void)hipEventRecord(before_fill, stream);
     const size_t lds = 3 * sizeof(int) * (size_t)L.nbins;
     if (M)
         hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
-                           n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst, M, Fn);
+                           n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst, M, Fn);
     else
         hipLaunchKernelGGL(k_bin_fill<false>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
-                           n, rp, col, L.bin_shift, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst,
+                           n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst,
                            nullptr, nullptr);
 }
 
@@ -708,7 +714,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
                 if (stats) stats->blocked_iterations++;
             } else if (bin_state == 1) {
-                hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bin_shift, L.nchunks, w.bcnt,
+                hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows, L.nchunks, w.bcnt,
                                    w.bsrc, w.bdst, F, Fn, G, w.M);
                 if (stats) stats->binned_iterations++;
             } else {

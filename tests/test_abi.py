@@ -50,6 +50,12 @@ def test_defaults_and_sizes():
     assert 0 < a < b
     # five int32[n] vectors at least
     assert binding.workspace_bytes(1 << 20, 0) >= 5 * 4 * (1 << 20)
+    # the binned layout's sizing (bin width chosen from n) on empty, tiny and
+    # large graphs: 6 bytes per stored entry on top of the plain workspace
+    binned, unbinned = binding.make_opts(binned=1), binding.make_opts(binned=0)
+    for n, nnz in ((0, 0), (1, 0), (5, 8), (1000, 1), (3_000_000, 6668), (1 << 24, 536_865_336)):
+        plain = binding.workspace_bytes(n, nnz, unbinned)
+        assert plain > 0 and binding.workspace_bytes(n, nnz, binned) >= plain + (6 * nnz if nnz else 0)
     lib = binding.load_library()
     assert lib.fastsv_strerror(0) == b"ok"
     assert b"max_iters" in lib.fastsv_strerror(-6)

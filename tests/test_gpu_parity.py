@@ -152,12 +152,13 @@ def test_sparse_rows_wide_windows(gpu_ok):
     rp_h, col_h = P.csr_from_pairs(n, pairs)
     g = gg.Graph("wide_windows", n, rp_h, col_h, len(pairs))
     check_graph(g, taus=(0.0, 1.0), trajectory=True)
-    # the same through the binned passes (92 bins, first iteration fused into
-    # the layout build at tau 0, built lazily at tau 1)
+    # the same through the binned passes (by default 256 bins, one per CU, of
+    # 11719 rows; first iteration fused into the layout build at tau 0, built
+    # lazily at tau 1)
     check_graph(g, taus=(0.0, 1.0), trajectory=True, binned=True)
     rp, col = to_dev(g)
     _, st = solve(rp, col, frontier_tau=0.0, binned=True)
-    assert st.num_bins == (n + 32767) // 32768 and st.bin_fused_first == 1
+    assert st.num_bins == 256 and st.bin_fused_first == 1
 
 
 def test_blocked_passes_trajectories(gpu_ok):
