@@ -115,11 +115,14 @@ class Server:
             ctypes.c_void_p(rp_p.ctypes.data), ctypes.c_void_p(col_p.ctypes.data), ctypes.c_void_p(lab_p.ctypes.data),
             ctypes.c_void_p(iters.ctypes.data), ctypes.c_void_p(tickets.ctypes.data), int(bool(mapped)),
             ctypes.byref(acc))
-        for i in range(acc.value):
-            self.pending[int(tickets[i])] = (labels[lab_off[i]:lab_off[i] + n[i]], iters[i:i + 1], rps[i], cols[i])
+        # one shared record per call; a ticket maps to (record, index), and the
+        # labels view is cut when the ticket is polled
+        rec = (labels, lab_off.tolist(), n.tolist(), iters, rps, cols)
+        tl = tickets.tolist()
+        self.pending.update(zip(tl[:acc.value], ((rec, i) for i in range(acc.value))))
         if st != B.FASTSV_OK:
             raise B.FastSVError(st, "fastsv_server_submit_batch")
-        return [int(t) for t in tickets]
+        return tl
 
     def step(self):
         r, q = ctypes.c_int32(), ctypes.c_int32()
@@ -137,9 +140,14 @@ class Server:
             st = self.lib.fastsv_server_poll(self.h, buf, cap, ctypes.byref(k))
             if st != B.FASTSV_OK:
                 raise B.FastSVError(st, "fastsv_server_poll")
-            for i in range(k.value):
-                lab, its, _, _ = self.pending.pop(buf[i])
-                out.append((buf[i], lab, int(its[0])))
+            for t in buf[:k.value]:
+                p = self.pending.pop(t)
+                if len(p) == 2:  # from submit_many: (shared record, index)
+                    (labels, off, n, iters, _, _), i = p
+                    out.append((t, labels[off[i]:off[i] + n[i]], int(iters[i])))
+                else:
+                    lab, its, _, _ = p
+                    out.append((t, lab, int(its[0])))
             if k.value < cap:
                 return out
 
