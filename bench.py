@@ -15,6 +15,9 @@ Also in the same JSON line:
                 events on the call's stream, against 8 TB/s; traffic = counter-
                 measured HBM bytes per launch (profiles/), null when the kernel
                 sources have changed since they were taken
+  solve_roofline  the same for the whole solve: the library's algorithmic
+                bytes of all executed iterations over the wall time per solve,
+                and the counter-measured bytes of all kernels of one solve
   cpu_baseline  the union-find oracle on the host, one core, the whole graph
   batched       4096 Erdos-Renyi graphs in one batched call vs one call per
                 graph (graphs/s)
@@ -145,6 +148,7 @@ def bench_solve(args, fs, torch, np):
     log("timed region")
     # every step of the solve is timed with HIP events on the call's stream
     gather_ms, gather_n, first_ms, sparse_ms, gp_ms, prep_ms = 0.0, 0, 0.0, 0.0, 0.0, 0.0
+    solve_alg = 0
     iters = []
     binned = fused = False
     torch.cuda.synchronize()
@@ -152,6 +156,7 @@ def bench_solve(args, fs, torch, np):
     for _ in range(args.steps):
         _, st = fs.cc_csr(rp, col, labels=labels, workspace=ws, timing=True, **kw)
         iters.append(st.iterations)
+        solve_alg = st.alg_bytes
         binned = st.binned_iterations > 0
         fused = st.bin_fused_first == 1
         prep_ms += st.ms_bin_prepare
@@ -188,6 +193,14 @@ def bench_solve(args, fs, torch, np):
                                        traffic_db))
     # the dominant kernel is the one with the most time per solve
     kernels.sort(key=lambda r: -r["ms_per_solve"])
+    # the whole solve: the library's count of algorithmic bytes over all executed
+    # iterations, over the wall time per solve; traffic = counter-measured bytes
+    # of all kernels of one solve
+    solve_ms = 1000.0 * elapsed / args.steps
+    srec = traffic_db.get("_solve") or {}
+    solve = {"alg_bytes": solve_alg, "ms": solve_ms, "achieved": solve_alg / (solve_ms * 1e-3) / 1e9,
+             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": solve_alg / (solve_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+             "traffic": srec.get("hbm_bytes_per_solve") if srec.get("kernel_source_sha256_16") == src_hash else None}
     res = {
         "value": g.m_eff * args.steps / elapsed,
         "ms_per_step": 1000.0 * elapsed / args.steps,
@@ -195,6 +208,7 @@ def bench_solve(args, fs, torch, np):
                        frontier_tau=args.tau),
         "roofline": kernels[0] if kernels else None,
         "roofline_other": kernels[1:],
+        "solve_roofline": solve,
         "breakdown_ms_per_solve": {"first_iteration": first_ms / args.steps, "bin_layout": prep_ms / args.steps,
                                    "dense_steps": gather_ms / args.steps, "sparse_push": sparse_ms / args.steps,
                                    "grandparent": gp_ms / args.steps},
@@ -397,6 +411,7 @@ def main():
         "config": res["config"],
         "roofline": res["roofline"],
         "roofline_other": res["roofline_other"],
+        "solve_roofline": res["solve_roofline"],
         "breakdown_ms_per_solve": res["breakdown_ms_per_solve"],
         "labels_match_oracle": res["labels_match_oracle"],
     }
