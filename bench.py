@@ -33,6 +33,7 @@ Also in the same JSON line:
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -364,12 +365,20 @@ def bench_serve(args, torch, np):
     serving.run_open_loop(srv, graphs[:64], np.zeros(64), mapped=True)
     srv.close()
     serving.run_plain(graphs[:64], np.zeros(64))
+    def settled():
+        # the host loops of both paths run in Python: collect once and freeze
+        # what exists, so that no full collection lands inside a timed run
+        gc.collect()
+        gc.freeze()
+
     for mode, arr in (("open_loop", tr.arrivals), ("saturation", np.zeros_like(tr.arrivals))):
         srv = server()
+        settled()
         lat, span, _ = serving.run_open_loop(srv, graphs, arr, mapped=True)
         s = srv.stats()
         srv.close()
         p50, p99 = pct(lat)
+        settled()
         lat_p, span_p, _ = serving.run_plain(graphs, arr)
         q50, q99 = pct(lat_p)
         out[mode] = {"server": {"graphs_per_s": len(graphs) / span, "p50_ms": p50, "p99_ms": p99,

@@ -24,7 +24,9 @@
 //      arrays in place from page-locked host memory (pageable ones are staged
 //      by DMA first), large or pageable column arrays go by DMA on the second
 //      copy stream, and the tiles are built.  The admitted graphs run from the
-//      next step on, or from this one when nothing else is resident.
+//      next step on (the one after while requests are still waiting, so that
+//      the copy streams stay a step ahead), or from this one when nothing
+//      else is resident.
 //   3. hooking, decided per graph: the dense pull over the graph's resident
 //      tiles in its first iteration and whenever its frontier (total degree of
 //      the grandparents that changed in the previous step) exceeds
@@ -61,7 +63,7 @@ struct Request {
     int32_t *iters_out;
 };
 
-// kStaged: placed (or being placed) on the copy stream, runs from the next step
+// kStaged: placed (or being placed) on the copy stream, runs from its start step
 enum SlotState : int { kFree = 0, kRunning = 1, kRetiring = 2, kStaged = 3 };
 
 // pinned requests at least this large have their column ids copied by the DMA
@@ -71,6 +73,12 @@ constexpr int64_t kSrvDmaMinEntries = 1 << 18;
 // a step's transfers then take about as long as its compute, and the copy
 // stream works on the next graphs while the resident ones iterate
 constexpr int64_t kSrvStepAdmitBytes = int64_t(128) << 20;
+// while requests are still waiting after a step's admission (a backlog), the
+// admitted graphs start two steps later instead of one, so that the copy
+// streams always hold the next step's transfers as well; kSrvGens admission
+// generations (events and host buffers) are then in flight at once
+constexpr int kSrvBacklogDepth = 2;
+constexpr int kSrvGens = kSrvBacklogDepth + 1;
 
 struct Slot {
     int state = kFree;
@@ -79,7 +87,8 @@ struct Slot {
     int64_t nnz = 0;
     int vb = 0, eb = 0, tb = 0, ntiles = 0;
     int64_t fedge = 0;  // frontier degree sum after its last iteration
-    int admit_step = 0, done_step = 0;
+    int admit_step = 0, done_step = 0;  // admit_step: the step of its first iteration
+    int gen = 0;                         // admission generation while staged
     int32_t *labels_out = nullptr;
     int32_t *iters_out = nullptr;
 };
@@ -148,9 +157,8 @@ struct fastsv_server {
     hipStream_t stream = nullptr;
     hipStream_t cs = nullptr;            // placement stream: admission overlaps the compute of a step
     hipStream_t ds = nullptr;            // DMA stream for large column arrays, beside the placement
-    hipEvent_t ev_placed[2] = {};        // on cs: the graphs admitted at a step are in the pool
-    hipEvent_t ev_dma[2] = {};           // on ds: their DMA'd column arrays are too
-    bool staged_pending = false;         // graphs placed at the previous step wait for their first iteration
+    hipEvent_t ev_placed[kSrvGens] = {};  // on cs: the graphs admitted at a step are in the pool
+    hipEvent_t ev_dma[kSrvGens] = {};     // on ds: their DMA'd column arrays are too
     fastsv_opts opts{};
     int64_t V = 0, E = 0, T = 0;
     int S = 0;
@@ -163,14 +171,15 @@ struct fastsv_server {
     const int **srcs;
     Tile *tiles, *step_tiles;
     Counters *ctr;
-    // pinned host mirrors; the admission ones are double-buffered by step
-    // parity, since the copy stream may still read one step's while the host
-    // prepares the next
+    // pinned host mirrors; the admission ones rotate over kSrvGens generations,
+    // since the copy streams may still read earlier steps' while the host
+    // prepares the next (a generation's buffers are free once its graphs have
+    // started, which is at most kSrvBacklogDepth steps after their admission)
     int *h_slot_vb = nullptr, *h_slot_n = nullptr, *h_flags = nullptr,
-        *h_off_b2[2] = {}, *h_out = nullptr, *h_off_ret = nullptr, *h_edges = nullptr, *h_off_dense = nullptr;
-    PlaceChunk *h_chunks2[2] = {};
-    SrvNew *h_desc2[2] = {}, *h_desc_ret = nullptr, *h_desc_dense = nullptr;
-    const int **h_srcs2[2] = {};
+        *h_off_b2[kSrvGens] = {}, *h_out = nullptr, *h_off_ret = nullptr, *h_edges = nullptr, *h_off_dense = nullptr;
+    PlaceChunk *h_chunks2[kSrvGens] = {};
+    SrvNew *h_desc2[kSrvGens] = {}, *h_desc_ret = nullptr, *h_desc_dense = nullptr;
+    const int **h_srcs2[kSrvGens] = {};
     RangeAlloc va, ea, ta;
     // ranges of graphs retired in the current step: allocatable from the next
     // step on, when their reset (compute stream) has completed, so that the
@@ -286,18 +295,18 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
               pinned(&s->h_edges, max_slots) && pinned(&s->h_desc_dense, max_slots) &&
               pinned(&s->h_off_dense, max_slots + 1) && pinned(&s->h_off_ret, max_slots + 1) &&
               pinned(&s->h_slot_vb, max_slots) && pinned(&s->h_slot_n, max_slots) && pinned(&s->h_flags, max_slots);
-    for (int b = 0; b < 2 && ok; ++b)
+    for (int b = 0; b < kSrvGens && ok; ++b)
         ok = pinned(&s->h_srcs2[b], 2 * (size_t)max_slots) && pinned(&s->h_desc2[b], max_slots) &&
              pinned(&s->h_chunks2[b], (size_t)max_place_chunks(s->V, s->E, s->S)) &&
              pinned(&s->h_off_b2[b], max_slots + 1);
     if (!ok) { fastsv_server_destroy(s); return FASTSV_ENOMEM; }
     // copy stream at the default priority, and its events
-    if (hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->ds, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_placed[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_placed[1], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_dma[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_dma[1], hipEventDisableTiming) != hipSuccess) {
+    bool evs_ok = hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamCreateWithFlags(&s->ds, hipStreamNonBlocking) == hipSuccess;
+    for (int g = 0; g < kSrvGens && evs_ok; ++g)
+        evs_ok = hipEventCreateWithFlags(&s->ev_placed[g], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&s->ev_dma[g], hipEventDisableTiming) == hipSuccess;
+    if (!evs_ok) {
         fastsv_server_destroy(s);
         return FASTSV_EHIP;
     }
@@ -332,12 +341,14 @@ void fastsv_server_destroy(fastsv_server *s) {
     if (s->pool) (void)hipFree(s->pool);
     for (void *h : {(void *)s->h_slot_vb, (void *)s->h_slot_n, (void *)s->h_flags, (void *)s->h_out,
                     (void *)s->h_desc_ret, (void *)s->h_off_ret, (void *)s->h_edges, (void *)s->h_desc_dense,
-                    (void *)s->h_off_dense, (void *)s->h_desc2[0], (void *)s->h_desc2[1], (void *)s->h_chunks2[0],
-                    (void *)s->h_chunks2[1], (void *)s->h_off_b2[0], (void *)s->h_off_b2[1], (void *)s->h_srcs2[0],
-                    (void *)s->h_srcs2[1]})
+                    (void *)s->h_off_dense})
         if (h) (void)hipHostFree(h);
-    for (hipEvent_t e : {s->ev_placed[0], s->ev_placed[1], s->ev_dma[0], s->ev_dma[1]})
-        if (e) (void)hipEventDestroy(e);
+    for (int g = 0; g < kSrvGens; ++g) {
+        for (void *h : {(void *)s->h_desc2[g], (void *)s->h_chunks2[g], (void *)s->h_off_b2[g], (void *)s->h_srcs2[g]})
+            if (h) (void)hipHostFree(h);
+        if (s->ev_placed[g]) (void)hipEventDestroy(s->ev_placed[g]);
+        if (s->ev_dma[g]) (void)hipEventDestroy(s->ev_dma[g]);
+    }
     if (s->cs) (void)hipStreamDestroy(s->cs);
     if (s->ds) (void)hipStreamDestroy(s->ds);
     delete s;
@@ -419,24 +430,27 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     hipStream_t st = s->stream;
     hipStream_t cs = s->cs;
     const int step = ++s->step;
-    const int par = step & 1;
+    const int gen = step % kSrvGens;
     IterCounters *ic_front = &s->ctr->it[(step + 1) & 1];  // frontier left by the previous step
     IterCounters *ic = &s->ctr->it[step & 1];
 
-    // 0. graphs placed by the previous step run from this one on, once their
-    //    placement (copy stream) is complete
-    int nrunning = 0;
-    if (s->staged_pending) {
-        SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[par ^ 1], 0));
-        SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[par ^ 1], 0));
-        for (Slot &sl : s->slots)
-            if (sl.state == kStaged) {
-                sl.state = kRunning;
-                sl.admit_step = step;
-            }
-        s->staged_pending = false;
+    // 0. staged graphs whose start step this is run from now on, once their
+    //    placement (copy streams) is complete
+    int nrunning = 0, nstaged = 0;
+    unsigned starting = 0;  // generations whose graphs start in this step
+    for (Slot &sl : s->slots) {
+        if (sl.state == kStaged && sl.admit_step == step) {
+            sl.state = kRunning;
+            starting |= 1u << sl.gen;
+        }
+        nrunning += sl.state == kRunning;
+        nstaged += sl.state == kStaged;
     }
-    for (const Slot &sl : s->slots) nrunning += sl.state == kRunning;
+    for (int g = 0; g < kSrvGens; ++g)
+        if (starting & (1u << g)) {
+            SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[g], 0));
+            SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[g], 0));
+        }
     // ranges retired by the previous step (its reset finished before that
     // step's synchronisation returned)
     for (auto &r : s->rel_v) s->va.release(r.first, r.second);
@@ -480,14 +494,14 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     //    resident graphs' whole-range kernels may touch (F = G = M = u,
     //    lastk = 0), so the placement and those kernels cannot disturb each
     //    other.  With nothing else resident the new graphs run in this step.
-    SrvNew *h_desc = s->h_desc2[par];
-    const int **h_srcs = s->h_srcs2[par];
-    int *h_off_b = s->h_off_b2[par];
-    PlaceChunk *h_chunks = s->h_chunks2[par];
+    SrvNew *h_desc = s->h_desc2[gen];
+    const int **h_srcs = s->h_srcs2[gen];
+    int *h_off_b = s->h_off_b2[gen];
+    PlaceChunk *h_chunks = s->h_chunks2[gen];
     int nnew = 0, new_rows = 0, nchunks = 0;
     int64_t staged = 0;
     std::vector<int> admitted;
-    const bool same_step = nrunning == 0;
+    const bool same_step = nrunning == 0 && nstaged == 0;
     int64_t admit_bytes = 0;
     while (!s->queue.empty() && (nnew == 0 || admit_bytes < kSrvStepAdmitBytes)) {
         if (s->free_slots.empty()) break;
@@ -511,7 +525,8 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         sl.tb = (int)tb;
         sl.ntiles = ntiles;
         sl.fedge = 0;
-        sl.admit_step = step + 1;
+        sl.admit_step = step + 1;  // or later, decided once the step's admission is complete
+        sl.gen = gen;
         sl.labels_out = r.labels_out;
         sl.iters_out = r.iters_out;
         admitted.push_back(k);
@@ -554,17 +569,17 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
                          s->vbase, s->lastk);
         launch_srv_tiles(cs, nnew, new_rows, s->desc, s->off_b, s->rp, s->tiles);
         SRV_TRY(hipGetLastError());
-        SRV_TRY(hipEventRecord(s->ev_placed[par], cs));
-        SRV_TRY(hipEventRecord(s->ev_dma[par], s->ds));
+        SRV_TRY(hipEventRecord(s->ev_placed[gen], cs));
+        SRV_TRY(hipEventRecord(s->ev_dma[gen], s->ds));
         if (same_step) {
-            SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[par], 0));
-            SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[par], 0));
+            SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[gen], 0));
+            SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[gen], 0));
             for (int k : admitted) {
                 s->slots[k].state = kRunning;
                 s->slots[k].admit_step = step;
             }
-        } else {
-            s->staged_pending = true;
+        } else if (!s->queue.empty()) {
+            for (int k : admitted) s->slots[k].admit_step = step + kSrvBacklogDepth;
         }
     }
 
