@@ -70,6 +70,7 @@ struct IterCounters {
 
 struct Counters {
     IterCounters it[2];
+    IterCounters fb;  // frontier list built from the changed-vertex mask
     int status;
     int pad[7];
 };
@@ -176,7 +177,11 @@ void launch_zero_iter(hipStream_t s, IterCounters *ic);
 // degree sum per graph at index vbase[u]
 void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
                         int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter,
-                        const int *vbase = nullptr, int *gedge = nullptr);
+                        const int *vbase = nullptr, int *gedge = nullptr, unsigned long long *fmask = nullptr);
+// The frontier list of the vertices marked in fmask (see k_frontier_from_mask);
+// fb ends as (count << 32 | degree sum).
+void launch_frontier_from_mask(hipStream_t s, int n, const unsigned long long *fmask, const int *rp, int *frontier,
+                               int *eoff, IterCounters *fb);
 void launch_fill(hipStream_t s, int n, int *x, int v);
 void launch_fill_iota(hipStream_t s, int n, int *x);
 

@@ -64,7 +64,7 @@ struct Layout {
     BinDiv bdiv;  // bin width W and the divisor for u / W
     int nbins, nchunks, chunk_tiles;
     int64_t bin_scan_len;
-    size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_tiles, off_ctr;
+    size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_fmask, off_tiles, off_ctr;
     size_t off_cbcol, off_segptr, off_segrow, off_cnte, off_cnts, off_sums_e, off_sums_s, off_cbtiles, off_info;
     size_t off_bsrc, off_bdst, off_bcnt, off_bsums;
     size_t total;
@@ -113,6 +113,7 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
     L.off_M = take(vec);
     L.off_frontier = take(vec);
     L.off_eoff = take(vec);
+    L.off_fmask = take(sizeof(unsigned long long) * (size_t)((n + kWave - 1) / kWave));
     L.off_tiles = take(sizeof(Tile) * (size_t)L.ntiles);
     L.off_ctr = take(sizeof(Counters));
     // automatic mode does not pick the blocked passes yet: on the measured
@@ -171,6 +172,7 @@ struct Workspace {
     int *M;
     int *frontier;
     int *eoff;
+    unsigned long long *fmask;  // changed vertices of the last grandparent pass, one bit each
     Tile *tiles;
     Counters *ctr;
     int *cb_col, *seg_ptr, *seg_row, *cnt_e, *cnt_s, *sums_e, *sums_s;
@@ -189,6 +191,7 @@ Workspace carve(void *base, const Layout &L) {
     w.M = reinterpret_cast<int *>(p + L.off_M);
     w.frontier = reinterpret_cast<int *>(p + L.off_frontier);
     w.eoff = reinterpret_cast<int *>(p + L.off_eoff);
+    w.fmask = reinterpret_cast<unsigned long long *>(p + L.off_fmask);
     w.tiles = reinterpret_cast<Tile *>(p + L.off_tiles);
     w.ctr = reinterpret_cast<Counters *>(p + L.off_ctr);
     if (L.cb) {
@@ -328,10 +331,18 @@ void launch_zero_iter(hipStream_t s, IterCounters *ic) {
 
 void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
                         int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter, const int *vbase,
-                        int *gedge) {
+                        int *gedge, unsigned long long *fmask) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_grandparent, dim3(grid_for(n, kGpBlockVerts)), dim3(kGpThreads), 0, s, n, Fn, G, next_fn, rp,
-                       frontier, eoff, ic, write_frontier, lastk, iter, vbase, gedge);
+                       frontier, eoff, ic, write_frontier, lastk, iter, vbase, gedge, fmask);
+}
+
+void launch_frontier_from_mask(hipStream_t s, int n, const unsigned long long *fmask, const int *rp, int *frontier,
+                               int *eoff, IterCounters *fb) {
+    if (n <= 0) return;
+    launch_zero_iter(s, fb);
+    hipLaunchKernelGGL(k_frontier_from_mask, dim3(grid_for(n, kGpBlockVerts)), dim3(kGpThreads), 0, s, n, fmask, rp,
+                       frontier, eoff, fb);
 }
 
 void launch_fill_iota(hipStream_t s, int n, int *x) {
@@ -388,7 +399,7 @@ struct fastsv_ctx {
     Counters *host_ctr = nullptr;  // pinned
     void *ws = nullptr;
     size_t ws_size = 0;
-    hipEvent_t ev[4] = {};
+    hipEvent_t ev[6] = {};  // iteration phases; [4], [5] bracket the frontier list build
     bool events = false;
 };
 
@@ -727,16 +738,39 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
         launch_zero_iter(stream, ic);
         const bool want_frontier = opts.frontier_tau > 0.0f;
-        launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 1 : 0, P.lastk, it,
-                           P.vbase);
+        launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 2 : 0, P.lastk, it,
+                           P.vbase, nullptr, w.fmask);
         HIP_TRY(hipGetLastError());
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
         HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
-        const int64_t edges = (int64_t)(hc->packed & 0xffffffffull);
         // read Fn[u], gather Fn[Fn[u]], read G[u], write G[u] and the next seed
-        alg += 20 * (int64_t)n + (want_frontier ? 16 * changed : 0);
+        // (with the frontier wanted: a mask bit per vertex)
+        alg += 20 * (int64_t)n + (want_frontier ? ((int64_t)n + 7) / 8 : 0);
+        // the frontier list, and its total degree which decides the next
+        // iteration's pass, are built from the mask only while a sparse pass is
+        // still possible: every changed vertex has at least one entry, and at
+        // the average degree the volume must not exceed twice the threshold
+        // (a larger volume, or no list, means a dense pass, whose iterate is
+        // the same)
+        int64_t edges = nnz + 1;
+        bool list_ready = false;
+        if (want_frontier && changed > 0 &&
+            (opts.frontier_tau >= 1.0f ||
+             ((double)changed <= tau_edges && (double)changed * (double)nnz <= 2.0 * tau_edges * (double)n))) {
+            if (timed) HIP_TRY(hipEventRecord(ctx->ev[4], stream));
+            launch_frontier_from_mask(stream, n, w.fmask, P.rp, w.frontier, w.eoff, &w.ctr->fb);
+            HIP_TRY(hipGetLastError());
+            if (timed) HIP_TRY(hipEventRecord(ctx->ev[5], stream));
+            HIP_TRY(hipMemcpyAsync(&ctx->host_ctr->fb, &w.ctr->fb, sizeof(IterCounters), hipMemcpyDeviceToHost,
+                                   stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            edges = (int64_t)(ctx->host_ctr->fb.packed & 0xffffffffull);
+            list_ready = true;
+            // mask, the marked rows' starts, ids and offsets written
+            alg += ((int64_t)n + 7) / 8 + 16 * changed;
+        }
         if (stats && ti < FASTSV_TRACE_ITERS) {
             stats->changed[ti] = changed;
             stats->sparse[ti] = sparse ? 1 : 0;
@@ -751,6 +785,12 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                     stats->ms_bin_prepare = c;
                     a -= c;
                 }
+                if (list_ready) {
+                    // the frontier list build counts with the grandparent pass
+                    float l = 0;
+                    HIP_TRY(hipEventElapsedTime(&l, ctx->ev[4], ctx->ev[5]));
+                    b += l;
+                }
                 stats->ms_hook[ti] = a;
                 stats->ms_gp[ti] = b;
             }
@@ -763,7 +803,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 stats->dense_iterations++;
             }
         }
-        frontier_ready = want_frontier;
+        frontier_ready = list_ready;
         prev_fcnt = changed;
         prev_edges = edges;
         if (changed == 0) break;

@@ -709,16 +709,19 @@ __global__ void k_cb_tiles(int nblk, const CbInfo *__restrict__ info, const int 
 // ---------------------------------------------------------------------------
 // Grandparent pass + termination test + frontier compaction.
 //   G_k[u] = Fn[Fn[u]];  changed = G_k[u] != G_{k-1}[u];  NextFn[u] = G_k[u]
-// The changed vertices are counted (termination test) and, when requested,
-// appended to the frontier list together with the exclusive prefix of their
-// degrees (the sparse push balances edge slots with it).  Count and degree sum
-// share one 64-bit counter (count in the high half), updated once per block.
+// The changed vertices are counted (termination test).  write_frontier = 1
+// also appends them to the frontier list together with the exclusive prefix
+// of their degrees (the sparse push balances edge slots with it);
+// write_frontier = 2 marks them in fmask instead (one bit per vertex, one word
+// per wave; no degrees are read), and k_frontier_from_mask builds the list and
+// its degree sum when a sparse iteration may follow.  Count and degree sum share one 64-bit
+// counter (count in the high half), updated once per block.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kGpThreads) void k_grandparent(
     int n, const int *__restrict__ Fn, int *__restrict__ G, int *__restrict__ next_fn,
     const int *__restrict__ rp, int *__restrict__ frontier, int *__restrict__ eoff,
     IterCounters *__restrict__ ctr, int write_frontier, int *__restrict__ lastk, int iter,
-    const int *__restrict__ vbase, int *__restrict__ gedge) {
+    const int *__restrict__ vbase, int *__restrict__ gedge, unsigned long long *__restrict__ fmask) {
     constexpr int kW = kGpThreads / kWave;
     __shared__ int s_cnt[kGpPerThread][kW];
     __shared__ int s_deg[kGpPerThread][kW];
@@ -744,7 +747,7 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
                 // lastk: iteration of the last change, per vertex, or per graph
                 // (at the graph's first vertex) when the graph bases are given
                 if (lastk) lastk[vbase ? vbase[u] : u] = iter;
-                if (write_frontier) deg[i] = rp[u + 1] - rp[u];
+                if (write_frontier == 1) deg[i] = rp[u + 1] - rp[u];
             }
         }
     }
@@ -778,6 +781,11 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
             s_cnt[i][wave] = __popcll(bal);
             s_deg[i][wave] = incl;
         }
+        // the wave's 64 consecutive vertices as one mask word; stored past the
+        // caches (plain 8-byte stores from every wave leave partly written
+        // lines in L2 that slowed the next dense step by ~8%)
+        const int u0 = base_u + i * kGpThreads + wave * kWave;
+        if (write_frontier == 2 && lane == 0 && u0 < n) __builtin_nontemporal_store(bal, fmask + u0 / kWave);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -793,7 +801,7 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
         s_base = c ? atomicAdd(&ctr->packed, (c << 32) | d) : 0ull;
     }
     __syncthreads();
-    if (!write_frontier) return;
+    if (write_frontier != 1) return;
     const unsigned long long b = s_base;
     const int bc = (int)(b >> 32), bd = (int)(b & 0xffffffffull);
 #pragma unroll
@@ -802,6 +810,65 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
             int u = base_u + i * kGpThreads + threadIdx.x;
             int pos = bc + s_cnt[i][wave] + rank[i];
             frontier[pos] = u;
+            eoff[pos] = bd + s_deg[i][wave] + dpre[i];
+        }
+    }
+}
+
+// The frontier list (ids and degree offsets, as k_grandparent's
+// write_frontier = 1 writes it) of the vertices marked in fmask, one bit per
+// vertex; ctr->packed must be zero on entry and ends as (count << 32 | degree
+// sum).  The list's order differs from that mode's, which nothing depends on.
+__global__ __launch_bounds__(kGpThreads) void k_frontier_from_mask(int n, const unsigned long long *__restrict__ fmask,
+                                                                   const int *__restrict__ rp,
+                                                                   int *__restrict__ frontier,
+                                                                   int *__restrict__ eoff,
+                                                                   IterCounters *__restrict__ ctr) {
+    constexpr int kW = kGpThreads / kWave;
+    __shared__ int s_cnt[kGpPerThread][kW];
+    __shared__ int s_deg[kGpPerThread][kW];
+    __shared__ unsigned long long s_base;
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const int base_u = blockIdx.x * kGpBlockVerts;
+    bool ch[kGpPerThread];
+    int rank[kGpPerThread], dpre[kGpPerThread];
+#pragma unroll
+    for (int i = 0; i < kGpPerThread; ++i) {
+        const int u0 = base_u + i * kGpThreads + wave * kWave;
+        const unsigned long long word = u0 < n ? fmask[u0 / kWave] : 0ull;
+        const int u = u0 + lane;
+        ch[i] = u < n && ((word >> lane) & 1ull);
+        const int deg = ch[i] ? rp[u + 1] - rp[u] : 0;
+        rank[i] = __popcll(word & ((1ull << lane) - 1ull));
+        const int incl = wave_incl_sum(deg);
+        dpre[i] = incl - deg;
+        if (lane == kWave - 1) {
+            s_cnt[i][wave] = __popcll(word);
+            s_deg[i][wave] = incl;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long c = 0, d = 0;
+        for (int i = 0; i < kGpPerThread; ++i)
+            for (int w = 0; w < kW; ++w) {
+                const int cc = s_cnt[i][w], dd = s_deg[i][w];
+                s_cnt[i][w] = (int)c;
+                s_deg[i][w] = (int)d;
+                c += cc;
+                d += dd;
+            }
+        s_base = c ? atomicAdd(&ctr->packed, (c << 32) | d) : 0ull;
+    }
+    __syncthreads();
+    const unsigned long long b = s_base;
+    const int bc = (int)(b >> 32), bd = (int)(b & 0xffffffffull);
+#pragma unroll
+    for (int i = 0; i < kGpPerThread; ++i) {
+        if (ch[i]) {
+            const int pos = bc + s_cnt[i][wave] + rank[i];
+            frontier[pos] = base_u + i * kGpThreads + wave * kWave + lane;
             eoff[pos] = bd + s_deg[i][wave] + dpre[i];
         }
     }
