@@ -62,9 +62,12 @@ typedef struct {
                                iteration bound, Sec. 2.4) */
     float frontier_tau;     /* sparse-frontier switch (Sec. 4.2): iteration k+1 pushes from the
                                changed grandparents of iteration k when their total degree is
-                               below frontier_tau * nnz.  0: always dense SpMV; >= 1: sparse
-                               whenever possible (from iteration 2 on).  The labels and iterates
-                               do not depend on it. */
+                               below frontier_tau * nnz.  The degree sum is only taken when the
+                               changed count c allows it (c <= frontier_tau * nnz and
+                               c * nnz / n <= 2 * frontier_tau * nnz); otherwise the next pass
+                               is dense.  0: always dense SpMV; >= 1: sparse whenever possible
+                               (from iteration 2 on).  The labels and iterates do not depend on
+                               it. */
     int32_t validate;       /* 1: check row_ptr (monotone, row_ptr[0] = 0, row_ptr[n] = nnz) and
                                every column id on the device before solving (FASTSV_ERANGE) */
     int32_t timing;         /* 1: time every kernel with HIP events on the call's stream
@@ -125,7 +128,8 @@ typedef struct {
     int64_t changed[FASTSV_TRACE_ITERS];  /* entries of gf changed in iteration k (k < 64) */
     int32_t sparse[FASTSV_TRACE_ITERS];   /* 1 if iteration k used the sparse push */
     float ms_hook[FASTSV_TRACE_ITERS];    /* hooking kernel time of iteration k (opts.timing) */
-    float ms_gp[FASTSV_TRACE_ITERS];      /* grandparent/termination kernel time (opts.timing) */
+    float ms_gp[FASTSV_TRACE_ITERS];      /* grandparent/termination kernel time, with the frontier list
+                                             build when one follows (opts.timing) */
 } fastsv_stats;
 
 /* Default options: no iteration cap, frontier_tau = 0.05, no validation, no timing,
