@@ -203,6 +203,16 @@ def test_binned_passes_trajectories(gpu_ok):
         assert st.binned_iterations == max(0, ref.iterations - 1), (g.name, st.binned_iterations)
 
 
+def test_binned_automatic_width(gpu_ok):
+    # more than 2^22 vertices: binned by default, with the automatic width of
+    # ceil(5e6 / 256) = 19532 rows (not a power of two), one bin per CU
+    g = gg.er(5_000_000, 15_000_000, seed=67)
+    check_graph(g, taus=(0.0, 0.05))
+    rp, col = to_dev(g)
+    _, st = solve(rp, col)
+    assert st.num_bins == 256 and st.binned_iterations > 0 and st.bin_fused_first == 1
+
+
 def test_binned_hub_and_unsorted_rows(gpu_ok):
     # a star centre with an entry in every bin, plus rows in random order
     n = 6000
