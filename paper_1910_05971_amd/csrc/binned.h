@@ -12,8 +12,10 @@
 // entries (u, v) with u in bin b are exactly the entries (v, u) of the CSR
 // whose column u falls in bin b; listing those in the CSR's own storage order
 // (rows v ascending) gives bin b's entries sorted by source v.  The layout
-// stores, per entry of bin b, the source v (int32) and the row offset u - bW
-// (uint16), bin after bin.  A dense iteration then runs one workgroup per
+// stores one 32-bit record per entry of bin b, bin after bin: the low 16 bits
+// of the source v above the row offset u - bW.  The high bits of v change
+// rarely along a bin, and marker records carry them (engine.h has the
+// format).  A dense iteration then runs one workgroup per
 // bin: it streams the bin's entries, gathers G[v] in ascending order of v,
 // and min-reduces into an LDS window of W rows.  The waves of a workgroup
 // advance through the bin in step, so that they gather from the same narrow
@@ -22,11 +24,12 @@
 // The minimum is order-free, so the iterate is bit-identical to the pull
 // pass's.
 //
-// Building the layout: a count pass (entries per chunk of tiles and bin), an
+// Building the layout: a count pass (records per chunk of tiles and bin), an
 // exclusive scan of the counts in bin-major order, which gives every
 // (bin, chunk) run its first position, and a fill pass that sorts each round
-// of tiles by bin in LDS and writes the runs (the order inside a run is not
-// fixed; no result depends on it).
+// of tiles by bin in LDS and writes the runs.  Inside a run, records follow
+// the marker of their high bits; their order is otherwise not fixed, and no
+// result depends on it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,12 +42,29 @@
 
 namespace fsv {
 
-// Entries per (chunk, bin) in bin-major order: cnt[b * nchunks + k].  Chunk
+// High bits of the sources of chunk k's rows: [lo, end] from the rows of its
+// first and last entries (end >= lo even for a malformed row_ptr, so that the
+// count and the fill pass agree on the number of markers).
+struct ChunkHi {
+    int lo, end;
+};
+__device__ __forceinline__ ChunkHi chunk_hi(const Tile *__restrict__ tiles, int ntiles, int k, int chunk_tiles) {
+    const int t_begin = k * chunk_tiles, t_end = min(t_begin + chunk_tiles, ntiles);
+    ChunkHi h;
+    h.lo = tiles[t_begin].r_lo >> kSrcLoBits;
+    h.end = max(tiles[t_end - 1].r_hi >> kSrcLoBits, h.lo);
+    return h;
+}
+
+// Records per (chunk, bin) in bin-major order: cnt[b * nchunks + k].  Chunk
 // k is the tiles [k * chunk_tiles, (k + 1) * chunk_tiles), i.e. the entries
-// from k * chunk_tiles * kTileEntries on.  Entries with a column id outside
-// [0, n) are not counted (and not placed by the fill pass).
+// from k * chunk_tiles * kTileEntries on.  A run holds the chunk's entries of
+// the bin and one marker for every value of the high source bits in the
+// chunk's row range.  Entries with a column id outside [0, n) are not counted
+// (and not placed by the fill pass).
 __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, const int *__restrict__ col,
-                                                           BinDiv bd, int nbins, int nchunks, int chunk_tiles,
+                                                           const Tile *__restrict__ tiles, int ntiles, BinDiv bd,
+                                                           int nbins, int nchunks, int chunk_tiles,
                                                            int *__restrict__ cnt) {
     __shared__ int hist[kMaxBins];
     const int tid = threadIdx.x;
@@ -69,7 +89,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
         }
     }
     __syncthreads();
-    for (int b = tid; b < nbins; b += kBinThreads) cnt[(int64_t)b * nchunks + k] = hist[b];
+    const ChunkHi ch = chunk_hi(tiles, ntiles, k, chunk_tiles);
+    const int markers = ch.end - ch.lo + 1;
+    for (int b = tid; b < nbins; b += kBinThreads) cnt[(int64_t)b * nchunks + k] = hist[b] + markers;
     if (k == 0 && tid == 0) cnt[(int64_t)nbins * nchunks] = 0;  // becomes the total after the scan
 }
 
@@ -77,6 +99,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
 // a time (one tile per wave).  Each round sorts its entries by bin in LDS and
 // writes every bin's run at the bin's cursor, which starts at the chunk's
 // offset from the scan: a (chunk, bin) run belongs to this workgroup only.
+// Before the first record with high source bits h, every bin's run gets the
+// marker of h, and of every value between the last one and h (values without
+// entries included, so that each run holds the count pass's number of
+// records).  A round whose rows share one value of the high bits (all but a
+// few rounds) is sorted once; one whose rows cross a boundary is processed
+// once per value in its row range, in ascending order.  Writes at or beyond
+// cap (only a malformed row_ptr gets there) are dropped.
 // With kFirst the pass also performs the first iteration of the method, whose
 // grandparent vector is the identity: m[u] = min N(u) (the column ids
 // themselves), and where m[u] < u, M[u] = Fn[u] = m[u] (both hooks target u,
@@ -86,10 +115,11 @@ template <bool kFirst>
 __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
                                                           const int *__restrict__ rp, const int *__restrict__ col,
                                                           BinDiv bd, int nbins, int nchunks, int chunk_tiles,
-                                                          const int *__restrict__ off, int *__restrict__ bsrc,
-                                                          unsigned short *__restrict__ bdst, int *__restrict__ M,
-                                                          int *__restrict__ Fn) {
+                                                          const int *__restrict__ off, int cap,
+                                                          unsigned *__restrict__ brec, int *__restrict__ bck,
+                                                          int *__restrict__ M, int *__restrict__ Fn) {
     constexpr int kWaves = kFillThreads / kWave;
+    constexpr int kCkMask = (1 << kBinCkShift) - 1;
     static_assert(kRowWin <= kTileEntries, "row windows and row minima share the staging arrays");
     extern __shared__ int s_dyn[];
     int *cur = s_dyn;               // next free position of the bin's run
@@ -99,21 +129,47 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
     __shared__ int su[kWaves * kTileEntries];  // staged columns
     __shared__ int s_wsum[kWaves];
     // the wave's window of row starts and (first iteration) its per-row minima
-    // live from the round's start to its third barrier, the staged entries
-    // from its fourth to its sixth, so they share memory
+    // live from the round's start to its second barrier, the staged entries
+    // after it, so they share memory
     int *winw = su + (threadIdx.x / kWave) * kRowWin;
     int *rminw = sv + (threadIdx.x / kWave) * kRowWin;
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = lane_id();
     const int k = xcd_major(blockIdx.x, gridDim.x);
+    const int t_end = min((k + 1) * chunk_tiles, ntiles);
+    const ChunkHi ch = chunk_hi(tiles, ntiles, k, chunk_tiles);
+    auto hi_of = [&](int row) { return min(max(row >> kSrcLoBits, ch.lo), ch.end); };
     for (int b = tid; b < nbins; b += kFillThreads) cur[b] = off[(int64_t)b * nchunks + k];
     const int per = (nbins + kFillThreads - 1) / kFillThreads;
     const int b0 = tid * per, b1 = min(b0 + per, nbins);
     for (int b = b0; b < b1; ++b) hist[b] = 0;
-    for (int t0 = k * chunk_tiles; t0 < min((k + 1) * chunk_tiles, ntiles); t0 += kWaves) {
+    // markers are in place for every value up to hi_done (the same in every thread)
+    int hi_done = ch.lo - 1;
+    // markers of (hi_done, h] at the cursors of this thread's bins
+    auto put_markers = [&](int h) {
+        for (int b = b0; b < b1; ++b) {
+            int pos = cur[b];
+            for (int x = hi_done + 1; x <= h; ++x, ++pos) {
+                if (pos >= cap) continue;
+                brec[pos] = ((unsigned)x << kSrcLoBits) | kBinMarker;
+                if ((pos & kCkMask) == 0) bck[pos >> kBinCkShift] = x;
+            }
+            cur[b] = pos;
+        }
+        hi_done = h;
+    };
+    for (int t0 = k * chunk_tiles; t0 < t_end; t0 += kWaves) {
+      // high source bits of the round's rows: one value unless they cross a
+      // boundary; then the round is processed once per value, each pass
+      // placing the entries of its value only
+      const int h_first = hi_of(tiles[t0].r_lo);
+      const int h_last = max(hi_of(tiles[min(t0 + kWaves, t_end) - 1].r_hi), h_first);
+      for (int h = h_first; h <= h_last; ++h) {
+        const bool one = h_first == h_last;
+        const bool first_pass = h == h_first;
         const int t = t0 + wave;
-        const bool tile_ok = t < min((k + 1) * chunk_tiles, ntiles);
+        const bool tile_ok = t < t_end;
         const Tile T = tile_ok ? tiles[t] : Tile{0, 0, 0, -1};
         const int a = T.e0 + lane * kPerLane;
         const int cnt = tile_ok ? max(0, min(kPerLane, T.e1 - a)) : 0;
@@ -163,10 +219,10 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
         }
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
-            const bool ok = j < cnt && c[j] >= 0 && c[j] < n;
+            const bool ok = j < cnt && c[j] >= 0 && c[j] < n && (one || hi_of(r[j]) == h);
             rank[j] = ok ? atomicAdd(&hist[bin_of(c[j], bd)], 1) : -1;
         }
-        if (kFirst && cnt > 0) {
+        if (kFirst && first_pass && cnt > 0) {
             // minimum column of every row segment of the lane: into the tile's
             // LDS row array, or straight to M / Fn for a tile whose rows are too
             // far apart for the window
@@ -187,7 +243,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
             else finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
         }
         __syncthreads();
-        if (kFirst && in_lds) {
+        if (kFirst && first_pass && in_lds) {
             // rows of the tile; a row that continues in a neighbouring tile
             // needs atomics, the others are written by this wave alone
             const int nrows = nwin - 1;
@@ -198,6 +254,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                 finish_row<true>(T.r_lo + i, m, shared_row, nullptr, Fn, nullptr, M);
             }
         }
+        if (h > hi_done) put_markers(h);
         // exclusive offsets of the round's bins in the stage
         int local = 0;
         for (int b = b0; b < b1; ++b) local += hist[b];
@@ -228,33 +285,39 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
             const int u = su[sidx];
             const int b = bin_of(u, bd);
             const int pos = cur[b] + (sidx - loff[b]);
-            bsrc[pos] = sv[sidx];
-            bdst[pos] = (unsigned short)(u - b * bd.rows);
+            if (pos < cap) {
+                brec[pos] = ((unsigned)sv[sidx] << kSrcLoBits) | (unsigned)(u - b * bd.rows);
+                if ((pos & kCkMask) == 0) bck[pos >> kBinCkShift] = h;
+            }
         }
         __syncthreads();
         for (int b = b0; b < b1; ++b) {
             cur[b] += hist[b];
             hist[b] = 0;
         }
-        // the next round's first barrier orders these updates before any use
+        // the next pass's first barrier orders these updates before any use
+      }
     }
+    if (ch.end > hi_done) put_markers(ch.end);
 }
 
 // Dense pass over the binned layout: one workgroup per bin, the bin's W rows
 // in LDS from the first entry to the last, then the rows are finished as in
 // the pull pass (M update, aggressive and stochastic hooks).  The bin's
 // entries are sorted by source, and the workgroup walks them in block-wide
-// steps of kWaves * kSpan consecutive entries with a barrier after each, so
+// steps of kWaves * kSpan consecutive records with a barrier after each, so
 // that its waves gather from the same narrow slice of G at the same time and
-// share its lines in L1 and L2.  All bins are launched at once; the device
-// starts later bins as earlier ones finish.
-__global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, const int *__restrict__ off,
-                                                   const int *__restrict__ bsrc,
-                                                   const unsigned short *__restrict__ bdst,
+// share its lines in L1 and L2.  The steps are aligned to the checkpoints, and
+// every wave rebuilds the full sources of its records from the checkpoint at
+// its first record and the markers among them.  All bins are launched at
+// once; the device starts later bins as earlier ones finish.
+__global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, int cap, const int *__restrict__ off,
+                                                   const unsigned *__restrict__ brec, const int *__restrict__ bck,
                                                    const int *__restrict__ F, int *__restrict__ Fn,
                                                    const int *__restrict__ G, int *__restrict__ M) {
     __shared__ int wmin[kBinRowsMax];
     constexpr int kSpan = kWave * kBinSpan;
+    static_assert(kSpan == 1 << kBinCkShift, "every wave starts at a checkpoint");
     constexpr int kWaves = 1024 / kWave;
     const int tid = threadIdx.x;
     const int lane = lane_id(), wave = tid / kWave;
@@ -262,34 +325,52 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, co
     const int u0 = b * W;
     const int rows = min(W, n - u0);
     for (int i = tid; i < rows; i += 1024) wmin[i] = INT_MAX;
-    const int p0 = off[(int64_t)b * nchunks], p1 = off[(int64_t)(b + 1) * nchunks];
+    const int p0 = off[(int64_t)b * nchunks], p1 = min(off[(int64_t)(b + 1) * nchunks], cap);
+    const unsigned long long upto = ~0ull >> (kWave - 1 - lane);  // lanes 0..lane
     __syncthreads();
     // the trip count is the same for every wave: the barrier is reached by all
-    for (int blk = p0; blk < p1; blk += kWaves * kSpan) {
+    for (int blk = p0 & ~(kSpan - 1); blk < p1; blk += kWaves * kSpan) {
         const int base = blk + wave * kSpan;
-        int v[kBinSpan], d[kBinSpan];
-        if (base + kSpan <= p1) {
+        if (base < p1) {
+            unsigned rec[kBinSpan];
+            if (base >= p0 && base + kSpan <= p1) {
 #pragma unroll
-            for (int x = 0; x < kBinSpan; ++x) {
-                v[x] = __builtin_nontemporal_load(bsrc + base + x * kWave + lane);
-                d[x] = __builtin_nontemporal_load(bdst + base + x * kWave + lane);
+                for (int x = 0; x < kBinSpan; ++x) rec[x] = __builtin_nontemporal_load(brec + base + x * kWave + lane);
+            } else {
+                // positions outside the bin read as markers; the bin's first
+                // record is a marker, which replaces what they carry
+#pragma unroll
+                for (int x = 0; x < kBinSpan; ++x) {
+                    const int q = base + x * kWave + lane;
+                    const unsigned r = __builtin_nontemporal_load(brec + min(max(q, p0), p1 - 1));
+                    rec[x] = q >= p0 && q < p1 ? r : kBinMarker;
+                }
             }
-#pragma unroll
-            for (int x = 0; x < kBinSpan; ++x) v[x] = G[v[x]];
-#pragma unroll
-            for (int x = 0; x < kBinSpan; ++x) atomicMin(&wmin[d[x]], v[x]);
-        } else if (base < p1) {
+            // high bits in force before the wave's first record
+            int carry = base >= p0 ? bck[base >> kBinCkShift] : 0;
+            int v[kBinSpan], d[kBinSpan];
 #pragma unroll
             for (int x = 0; x < kBinSpan; ++x) {
-                const int p = min(base + x * kWave + lane, p1 - 1);
-                v[x] = __builtin_nontemporal_load(bsrc + p);
-                d[x] = __builtin_nontemporal_load(bdst + p);
+                const unsigned r = rec[x];
+                const bool mk = (r & 0xFFFFu) == kBinMarker;
+                const unsigned long long mm = __ballot(mk);
+                const int lo = (int)(r >> kSrcLoBits);
+                // the last marker at or before this lane, else the carry
+                const unsigned long long le = mm & upto;
+                const int from = le ? kWave - 1 - __clzll(le) : lane;
+                const int hb = __builtin_amdgcn_ds_bpermute(from << 2, lo);
+                const int hi = le ? hb : carry;
+                const int lv = __builtin_amdgcn_readlane(lo, mm ? kWave - 1 - __clzll(mm) : 0);
+                carry = mm ? lv : carry;
+                const int dd = (int)(r & 0xFFFFu);
+                d[x] = mk || dd >= rows ? -1 : dd;  // (a row offset beyond the bin is never written)
+                v[x] = mk ? 0 : (int)min(((unsigned)hi << kSrcLoBits) | (unsigned)lo, (unsigned)(n - 1));
             }
 #pragma unroll
             for (int x = 0; x < kBinSpan; ++x) v[x] = G[v[x]];
 #pragma unroll
             for (int x = 0; x < kBinSpan; ++x)
-                if (base + x * kWave + lane < p1) atomicMin(&wmin[d[x]], v[x]);
+                if (d[x] >= 0) atomicMin(&wmin[d[x]], v[x]);
         }
         __syncthreads();
     }

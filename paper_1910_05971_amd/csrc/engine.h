@@ -105,6 +105,19 @@ __host__ __device__ inline int xcd_major(int bid, int nblocks) {
 }
 constexpr int kBinAutoMinN = 1 << 22;   // automatic mode: graphs with more vertices (G well beyond L2)
 
+// One 32-bit record per layout entry: the low kSrcLoBits bits of the source
+// above the row offset inside the bin.  The high bits of the source are
+// carried by marker records (row offset kBinMarker, high bits above it) that
+// open every (bin, chunk) run and every new value of the high bits inside it;
+// a bin's sources ascend, so a record takes the high bits of the last marker
+// before it.  kBinCkShift: the high bits in force at every position that is a
+// multiple of 2^kBinCkShift are also stored in a checkpoint array, where a
+// wave of the dense pass starts.
+constexpr int kSrcLoBits = 16;
+constexpr unsigned kBinMarker = 0xFFFFu;
+constexpr int kBinCkShift = 10;
+static_assert(kBinRowsMax < (int)kBinMarker, "a row offset never equals the marker tag");
+
 // A graph entering or leaving the serving pool (see server.hip).
 struct SrvNew {
     int vb, eb, n, nnz;  // pool vertex base, pool entry base, vertices, entries

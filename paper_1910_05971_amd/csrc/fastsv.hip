@@ -64,9 +64,10 @@ struct Layout {
     BinDiv bdiv;  // bin width W and the divisor for u / W
     int nbins, nchunks, chunk_tiles;
     int64_t bin_scan_len;
+    int bin_cap;     // records the binned layout can hold (entries plus markers)
     size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_fmask, off_tiles, off_ctr;
     size_t off_cbcol, off_segptr, off_segrow, off_cnte, off_cnts, off_sums_e, off_sums_s, off_cbtiles, off_info;
-    size_t off_bsrc, off_bdst, off_bcnt, off_bsums;
+    size_t off_brec, off_bck, off_bcnt, off_bsums;
     size_t total;
 };
 
@@ -136,9 +137,9 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
         L.off_cbtiles = take(sizeof(Tile) * (size_t)(L.ntiles + kMaxBlocks));
         L.off_info = take(sizeof(CbInfo));
     }
-    // binned dense passes: per stored entry its source (int32) and row offset
-    // in the bin (uint16), the (bin, chunk) counts and their scan, the slice
-    // table of the dense pass
+    // binned dense passes: one 32-bit record per stored entry and per marker
+    // (see engine.h), the checkpoints of the high source bits, the
+    // (bin, chunk) counts and their scan
     // automatic width: the fewest bins that are a multiple of the CU count
     // (the dense pass then runs whole rounds of one workgroup per CU) with at
     // most kBinRowsMax rows each
@@ -158,10 +159,23 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
         L.chunk_tiles = (int)ct;
         L.nchunks = (int)((L.ntiles + ct - 1) / ct);
         L.bin_scan_len = nb * L.nchunks + 1;
-        L.off_bsrc = take(sizeof(int) * (size_t)nnz);
-        L.off_bdst = take(sizeof(unsigned short) * (size_t)nnz);
-        L.off_bcnt = take(sizeof(int) * (size_t)L.bin_scan_len);
-        L.off_bsums = take(sizeof(int) * (size_t)(grid_for(L.bin_scan_len, kScanBlock) + 1));
+        // markers: per bin, one per chunk and one per boundary of the high
+        // source bits inside a chunk's rows; the chunks' row ranges follow
+        // each other, so the boundaries are at most (n - 1) >> kSrcLoBits
+        const int64_t markers = nb * (L.nchunks + ((n - 1) >> kSrcLoBits));
+        const int64_t cap = nnz + markers;
+        // positions are int; the automatic mode also skips graphs so sparse
+        // that markers would be more than a quarter of the records
+        if (cap + (int64_t)kBinSpan * 1024 >= INT32_MAX || (lo.bin_mode == -1 && 4 * markers > nnz)) {
+            L.bin = false;
+            L.nbins = L.nchunks = 0;
+        } else {
+            L.bin_cap = (int)cap;
+            L.off_brec = take(sizeof(unsigned) * (size_t)cap);
+            L.off_bck = take(sizeof(int) * (size_t)((cap >> kBinCkShift) + 1));
+            L.off_bcnt = take(sizeof(int) * (size_t)L.bin_scan_len);
+            L.off_bsums = take(sizeof(int) * (size_t)(grid_for(L.bin_scan_len, kScanBlock) + 1));
+        }
     }
     L.total = p;
     return L;
@@ -178,8 +192,8 @@ struct Workspace {
     int *cb_col, *seg_ptr, *seg_row, *cnt_e, *cnt_s, *sums_e, *sums_s;
     Tile *cb_tiles;
     CbInfo *info;
-    int *bsrc;
-    unsigned short *bdst;
+    unsigned *brec;
+    int *bck;
     int *bcnt, *bsums;
 };
 
@@ -206,8 +220,8 @@ Workspace carve(void *base, const Layout &L) {
         w.info = reinterpret_cast<CbInfo *>(p + L.off_info);
     }
     if (L.bin) {
-        w.bsrc = reinterpret_cast<int *>(p + L.off_bsrc);
-        w.bdst = reinterpret_cast<unsigned short *>(p + L.off_bdst);
+        w.brec = reinterpret_cast<unsigned *>(p + L.off_brec);
+        w.bck = reinterpret_cast<int *>(p + L.off_bck);
         w.bcnt = reinterpret_cast<int *>(p + L.off_bcnt);
         w.bsums = reinterpret_cast<int *>(p + L.off_bsums);
     }
@@ -251,17 +265,18 @@ void cb_prepare(const Layout &L, const Workspace &w, const int *rp, const int *c
 // still the identity).
 void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream,
                  int *M = nullptr, int *Fn = nullptr, hipEvent_t before_fill = nullptr) {
-    hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, L.bdiv,
-                       L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
+    hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, w.tiles,
+                       (int)L.ntiles, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
     scan_inplace(w.bcnt, L.bin_scan_len, w.bsums, stream);
     if (before_fill) (void)hipEventRecord(before_fill, stream);
     const size_t lds = 3 * sizeof(int) * (size_t)L.nbins;
     if (M)
         hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
-                           n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst, M, Fn);
+                           n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, L.bin_cap, w.brec, w.bck,
+                           M, Fn);
     else
         hipLaunchKernelGGL(k_bin_fill<false>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
-                           n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, w.bsrc, w.bdst,
+                           n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, L.bin_cap, w.brec, w.bck,
                            nullptr, nullptr);
 }
 
@@ -725,8 +740,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
                 if (stats) stats->blocked_iterations++;
             } else if (bin_state == 1) {
-                hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows, L.nchunks, w.bcnt,
-                                   w.bsrc, w.bdst, F, Fn, G, w.M);
+                hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows, L.nchunks,
+                                   L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M);
                 if (stats) stats->binned_iterations++;
             } else {
                 launch_dense(stream, base ? kDenseBaseGather : kDenseGather, w.tiles, (int)ntiles, P.rp, P.col,

@@ -51,11 +51,22 @@ def test_defaults_and_sizes():
     # five int32[n] vectors at least
     assert binding.workspace_bytes(1 << 20, 0) >= 5 * 4 * (1 << 20)
     # the binned layout's sizing (bin width chosen from n) on empty, tiny and
-    # large graphs: 6 bytes per stored entry on top of the plain workspace
+    # large graphs: a 4-byte record per stored entry and per marker on top of
+    # the plain workspace
     binned, unbinned = binding.make_opts(binned=1), binding.make_opts(binned=0)
     for n, nnz in ((0, 0), (1, 0), (5, 8), (1000, 1), (3_000_000, 6668), (1 << 24, 536_865_336)):
         plain = binding.workspace_bytes(n, nnz, unbinned)
-        assert plain > 0 and binding.workspace_bytes(n, nnz, binned) >= plain + (6 * nnz if nnz else 0)
+        assert plain > 0 and binding.workspace_bytes(n, nnz, binned) >= plain + (4 * nnz if nnz else 0)
+    # R-MAT scale 24: 512 bins, 16,384 chunks, at most 512 * (16,384 + 255)
+    # markers, under 2% of the entries
+    n, nnz = 1 << 24, 536_865_336
+    extra = binding.workspace_bytes(n, nnz, binned) - binding.workspace_bytes(n, nnz, unbinned)
+    assert 4 * nnz < extra < 4.2 * nnz
+    # the automatic mode leaves out graphs so sparse that markers would exceed
+    # a quarter of the entries (2^23 vertices: 256 bins, 127 boundaries)
+    auto = binding.default_opts()
+    assert binding.workspace_bytes(1 << 23, 100_000, auto) == binding.workspace_bytes(1 << 23, 100_000, unbinned)
+    assert binding.workspace_bytes(1 << 23, 16 << 20, auto) > binding.workspace_bytes(1 << 23, 16 << 20, unbinned)
     lib = binding.load_library()
     assert lib.fastsv_strerror(0) == b"ok"
     assert b"max_iters" in lib.fastsv_strerror(-6)

@@ -213,6 +213,37 @@ def test_binned_automatic_width(gpu_ok):
     assert st.num_bins == 256 and st.binned_iterations > 0 and st.bin_fused_first == 1
 
 
+def test_binned_source_high_bits(gpu_ok):
+    # graphs beyond 2^16 vertices, where the layout's records carry the low 16
+    # bits of the source and markers the high bits:
+    # * ER: tiles and fill rounds whose rows cross a multiple of 2^16;
+    # * clusters far apart: one round whose rows span all 16 values of the high
+    #   bits of a 10^6-vertex graph, most of them without entries (markers only);
+    # * stars centred on both sides of a boundary, whose rows straddle tiles.
+    g = gg.er(400_000, 1_200_000, seed=71)
+    for shift in (12, 15):
+        check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift)
+    n = 1_000_000
+    starts = (0, 70_000, 131_000, 300_000, 655_300, 999_900)
+    pairs = []
+    for s0 in starts:
+        pairs += [(s0 + i, s0 + i + 1) for i in range(99)]
+    pairs += [(starts[i] + 50, starts[i + 1] + 7) for i in range(0, len(starts) - 1, 2)]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    clusters = gg.Graph("far_clusters", n, rp_h, col_h, len(pairs))
+    for shift in (12, 15):
+        check_graph(clusters, taus=(0.0, 1.0), trajectory=True, binned=True, bin_shift=shift)
+    rng = np.random.default_rng(72)
+    n = 300_000
+    pairs = [(65_535, int(v)) for v in rng.choice(n, 3000, replace=False) if v != 65_535]
+    pairs += [(65_536, int(v)) for v in rng.choice(n, 3000, replace=False) if v != 65_536]
+    pairs += [(131_071, int(v)) for v in rng.choice(n, 2000, replace=False) if v != 131_071]
+    pairs += [(int(a), int(b)) for a, b in rng.integers(0, n, size=(20_000, 2)) if a != b]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    stars = gg.Graph("boundary_stars", n, rp_h, col_h, len(pairs))
+    check_graph(stars, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=13)
+
+
 def test_binned_hub_and_unsorted_rows(gpu_ok):
     # a star centre with an entry in every bin, plus rows in random order
     n = 6000
