@@ -120,17 +120,18 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                                                           int *__restrict__ M, int *__restrict__ Fn) {
     constexpr int kWaves = kFillThreads / kWave;
     constexpr int kCkMask = (1 << kBinCkShift) - 1;
-    static_assert(kRowWin <= kTileEntries, "row windows and row minima share the staging arrays");
+    static_assert(2 * kRowWin <= kTileEntries, "row windows, row minima and the regrouped loads share the staging arrays");
     extern __shared__ int s_dyn[];
     int *cur = s_dyn;               // next free position of the bin's run
     int *hist = s_dyn + nbins;      // round's count per bin
     int *loff = s_dyn + 2 * nbins;  // round's exclusive offset per bin in the stage
-    __shared__ int sv[kWaves * kTileEntries];  // staged sources
-    __shared__ int su[kWaves * kTileEntries];  // staged columns
+    __shared__ __align__(16) int sv[kWaves * kTileEntries];  // staged sources
+    __shared__ __align__(16) int su[kWaves * kTileEntries];  // staged columns
     __shared__ int s_wsum[kWaves];
     // the wave's window of row starts and (first iteration) its per-row minima
     // live from the round's start to its second barrier, the staged entries
-    // after it, so they share memory
+    // after it, so they share memory (the windows and minima of all waves take
+    // the first halves of su and sv; whole tiles are regrouped in the second)
     int *winw = su + (threadIdx.x / kWave) * kRowWin;
     int *rminw = sv + (threadIdx.x / kWave) * kRowWin;
     const int tid = threadIdx.x;
@@ -174,11 +175,16 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
         const int a = T.e0 + lane * kPerLane;
         const int cnt = tile_ok ? max(0, min(kPerLane, T.e1 - a)) : 0;
         int c[kPerLane];
-        if (cnt == kPerLane && ((reinterpret_cast<uintptr_t>(col + a) & 15) == 0)) {
-            const v4i *p = reinterpret_cast<const v4i *>(col + a);
+        // a whole tile is read with loads of 1 KB each and regrouped through
+        // LDS after the barrier below, so that every lane then holds 16
+        // consecutive entries; other tiles are read entry by entry
+        const bool whole = tile_ok && T.e1 - T.e0 == kTileEntries &&
+                           ((reinterpret_cast<uintptr_t>(col + T.e0) & 15) == 0);
+        if (whole) {
+            const v4i *p = reinterpret_cast<const v4i *>(col + T.e0) + lane;
 #pragma unroll
             for (int q = 0; q < kPerLane / 4; ++q) {
-                v4i v = __builtin_nontemporal_load(p + q);
+                const v4i v = __builtin_nontemporal_load(p + q * kWave);
                 c[4 * q] = v.x; c[4 * q + 1] = v.y; c[4 * q + 2] = v.z; c[4 * q + 3] = v.w;
             }
         } else {
@@ -194,6 +200,33 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                 if (kFirst) rminw[j] = INT_MAX;
             }
         __syncthreads();
+        if (whole) {
+            // tile entries [0, 512) pass through su, [512, 1024) through sv,
+            // past the row windows and row minima of all waves (the first
+            // kWaves * kRowWin ints of each); nothing else is there before the
+            // round's entries are staged
+            constexpr int kHalf = kTileEntries / 2;
+            int *lo_half = su + kWaves * kRowWin + wave * kHalf;
+            int *hi_half = sv + kWaves * kRowWin + wave * kHalf;
+#pragma unroll
+            for (int q = 0; q < kPerLane / 4; ++q) {
+                const int x = 4 * lane + 4 * kWave * q;
+                *reinterpret_cast<v4i *>(x < kHalf ? lo_half + x : hi_half + (x - kHalf)) =
+                    v4i{c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]};
+            }
+            // LDS operations of one wave take effect in order; this keeps the
+            // compiler from moving the reads above the writes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int x0 = kPerLane * lane;
+            const v4i *mine = reinterpret_cast<const v4i *>(x0 < kHalf ? lo_half + x0 : hi_half + (x0 - kHalf));
+#pragma unroll
+            for (int q = 0; q < kPerLane / 4; ++q) {
+                const v4i w = mine[q];
+                c[4 * q] = w.x; c[4 * q + 1] = w.y; c[4 * q + 2] = w.z; c[4 * q + 3] = w.w;
+            }
+        }
         const int *wrow = winw;
         auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
         // source row of every entry and its rank inside its bin in this round
