@@ -190,11 +190,12 @@ def test_blocked_unsorted_rows_fall_back(gpu_ok):
 
 def test_binned_passes_trajectories(gpu_ok):
     # binned dense passes forced on moderate graphs with narrow bins: many bins,
-    # bins shorter than one block-wide span of the dense pass (16384 entries),
-    # and bins of several spans with a ragged last one (the R-MAT at shift 10)
+    # bins shorter than one block-wide span of the dense pass (32768 entries),
+    # and bins of one or several spans with a ragged last one (the R-MAT at
+    # shift 10: about 32K entries per bin, at shift 12: about 131K)
     graphs = [(gg.rmat(14, 16, seed=61), 8), (gg.er(30000, 120000, seed=62), 8),
               (gg.grid(120, 150, 0.6, seed=63), 8), (gg.rmat(16, 8, seed=64), 8), (gg.er(40000, 90000, seed=65), 10),
-              (gg.rmat(16, 16, seed=66), 10)]
+              (gg.rmat(16, 16, seed=66), 10), (gg.rmat(16, 16, seed=68), 12)]
     for g, shift in graphs:
         ref = check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift)
         rp, col = to_dev(g)
