@@ -974,6 +974,10 @@ __global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
             }
             if (val == INT_MAX) continue;
             int u = col[row + (s - off)] + vb;
+            // M only decreases: a push that a plain read shows cannot lower
+            // M[u] would change nothing (the atomic would return old <= val,
+            // and no hook follows), so it stays a load
+            if (val >= M[u]) continue;
             int old = atomicMin(M + u, val);
             if (val < old && val < G[u]) hook_row(u, val, F, Fn);
         }
