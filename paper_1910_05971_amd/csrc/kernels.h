@@ -81,25 +81,49 @@ __device__ __forceinline__ void finish_row(int u, int m, bool shared_row, const 
 // absolute row_ptr values) and whose entries are [e_begin, e_end): tile t
 // covers entries [e_begin + t*T, min(e_begin + (t+1)*T, e_end)).  The row
 // holding a tile's first entry writes r_lo, the row holding its last entry
-// writes r_hi; every tile gets exactly one writer of each.
+// writes r_hi; every tile gets exactly one writer of each.  A row over more
+// than kTileLongRow tiles (a hub) is handed to the whole block, so that no
+// thread loops over thousands of tiles.  Launched with 256 threads per block.
 // ---------------------------------------------------------------------------
-__global__ void k_build_tiles(int nrows, int r_begin, int e_begin, int e_end, const int *__restrict__ rp,
-                              Tile *__restrict__ tiles) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
-    const int r = r_begin + i;
-    const int s = rp[r] - e_begin, e = rp[r + 1] - e_begin;
-    if (s >= e) return;
+constexpr int kTileLongRow = 8;
+__global__ __launch_bounds__(256) void k_build_tiles(int nrows, int r_begin, int e_begin, int e_end,
+                                                     const int *__restrict__ rp, Tile *__restrict__ tiles) {
+    __shared__ int s_n;
+    __shared__ int s_row[256], s_s[256], s_e[256];
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     const int len = e_end - e_begin;
-    for (int t = s / kTileEntries; t <= (e - 1) / kTileEntries; ++t) {
-        int t0 = t * kTileEntries;
-        int last = min(t0 + kTileEntries, len) - 1;
+    auto put = [&](int r, int s, int e, int t) {
+        const int t0 = t * kTileEntries;
+        const int last = min(t0 + kTileEntries, len) - 1;
         if (t0 >= s && t0 < e) {
             tiles[t].e0 = e_begin + t0;
             tiles[t].e1 = e_begin + last + 1;
             tiles[t].r_lo = r;
         }
         if (last >= s && last < e) tiles[t].r_hi = r;
+    };
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nrows) {
+        const int r = r_begin + i;
+        const int s = rp[r] - e_begin, e = rp[r + 1] - e_begin;
+        if (s < e) {
+            const int ta = s / kTileEntries, tb = (e - 1) / kTileEntries;
+            if (tb - ta < kTileLongRow) {
+                for (int t = ta; t <= tb; ++t) put(r, s, e, t);
+            } else {
+                const int k = atomicAdd(&s_n, 1);
+                s_row[k] = r;
+                s_s[k] = s;
+                s_e[k] = e;
+            }
+        }
+    }
+    __syncthreads();
+    const int nlong = s_n;
+    for (int k = 0; k < nlong; ++k) {
+        const int r = s_row[k], s = s_s[k], e = s_e[k];
+        for (int t = s / kTileEntries + (int)threadIdx.x; t <= (e - 1) / kTileEntries; t += blockDim.x) put(r, s, e, t);
     }
 }
 
