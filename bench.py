@@ -8,7 +8,8 @@ resident in HBM; value = undirected edges per second.
 
 Also in the same JSON line:
   roofline      the kernel with the most time per solve, of the binned dense
-                SpMV step (k_bin_pull, one launch per iteration) and the layout
+                SpMV step (k_bin_pull<32> for R-MAT scale 24, whose bins are long
+                enough for the wide step, else <16>; one launch per iteration) and the layout
                 fill that also performs the first iteration (k_bin_fill<true>,
                 once per solve); the other one is in roofline_other.  Each:
                 algorithmic bytes per launch / its average launch time from HIP
@@ -152,6 +153,7 @@ def bench_solve(args, fs, torch, np):
     solve_alg = 0
     iters = []
     binned = fused = False
+    span = 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -159,6 +161,7 @@ def bench_solve(args, fs, torch, np):
         iters.append(st.iterations)
         solve_alg = st.alg_bytes
         binned = st.binned_iterations > 0
+        span = st.bin_span
         fused = st.bin_fused_first == 1
         prep_ms += st.ms_bin_prepare
         for k in range(min(st.iterations, 64)):
@@ -183,14 +186,15 @@ def bench_solve(args, fs, torch, np):
     kernels = []
     if gather_n:
         # one dense SpMV step (one launch): row_ptr, col, the G[col] gathers, then G, F, M per row
-        kernels.append(roofline_record("k_bin_pull" if binned else "k_tile_reduce<kGather>",
+        kernels.append(roofline_record(f"k_bin_pull<{span}>" if binned else "k_tile_reduce<kGather>",
                                        "one dense SpMV step", 4 * (n + 1) + 8 * nnz + 12 * n,
                                        gather_ms, gather_n, args.steps, src_hash, traffic_db))
     if fused and first_ms > 0:
         # the layout fill that also performs the first iteration: col and row_ptr
-        # read, the source and row-offset arrays written, M and Fn written per row
+        # read, one 4-byte record per entry written (the markers, at most 256 per
+        # bin, are left out), M and Fn written per row
         kernels.append(roofline_record("k_bin_fill<true>", "layout fill fused with the first iteration",
-                                       10 * nnz + 12 * n + 4, first_ms, args.steps, args.steps, src_hash,
+                                       8 * nnz + 12 * n + 4, first_ms, args.steps, args.steps, src_hash,
                                        traffic_db))
     # the dominant kernel is the one with the most time per solve
     kernels.sort(key=lambda r: -r["ms_per_solve"])

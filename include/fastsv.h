@@ -119,6 +119,8 @@ typedef struct {
     int32_t num_bins;              /* bins of the binned layout (0 when it was not built) */
     int32_t bin_fused_first;       /* 1 if the layout's fill pass also performed the first
                                       iteration (that pass is then ms_hook[0]) */
+    int32_t bin_span;              /* records per lane and step of the binned dense pass that
+                                      ran (16, or 32 for bins of at least 2^18 records; 0 if none) */
     float ms_bin_prepare;          /* time to build the binned layout; with bin_fused_first only
                                       its count and scan before the fill (opts.timing) */
     int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */

@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("sparse_iterations", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
                 ("blocked_prepared", ctypes.c_int32), ("blocked_iterations", ctypes.c_int32),
                 ("binned_iterations", ctypes.c_int32), ("num_bins", ctypes.c_int32),
-                ("bin_fused_first", ctypes.c_int32), ("ms_bin_prepare", ctypes.c_float),
+                ("bin_fused_first", ctypes.c_int32), ("bin_span", ctypes.c_int32), ("ms_bin_prepare", ctypes.c_float),
                 ("frontier_edges", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
                 ("ms_total", ctypes.c_double),
                 ("changed", ctypes.c_int64 * TRACE_ITERS), ("sparse", ctypes.c_int32 * TRACE_ITERS),

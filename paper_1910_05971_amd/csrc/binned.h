@@ -43,24 +43,28 @@
 namespace fsv {
 
 // High bits of the sources of chunk k's rows: [lo, end] from the rows of its
-// first and last entries (end >= lo even for a malformed row_ptr, so that the
-// count and the fill pass agree on the number of markers).
+// first and last entries, and prev, the value in force along every bin when
+// the chunk's run starts: the last value of chunk k - 1 (every run carries
+// the markers of all values of its chunk up to end), -1 before chunk 0.  A
+// run therefore holds the markers of (prev, end].  end >= lo >= prev even
+// for a malformed row_ptr, so that the count and the fill pass agree.
 struct ChunkHi {
-    int lo, end;
+    int prev, lo, end;
 };
 __device__ __forceinline__ ChunkHi chunk_hi(const Tile *__restrict__ tiles, int ntiles, int k, int chunk_tiles) {
     const int t_begin = k * chunk_tiles, t_end = min(t_begin + chunk_tiles, ntiles);
     ChunkHi h;
     h.lo = tiles[t_begin].r_lo >> kSrcLoBits;
     h.end = max(tiles[t_end - 1].r_hi >> kSrcLoBits, h.lo);
+    h.prev = k == 0 ? -1 : min(tiles[t_begin - 1].r_hi >> kSrcLoBits, h.lo);
     return h;
 }
 
 // Records per (chunk, bin) in bin-major order: cnt[b * nchunks + k].  Chunk
 // k is the tiles [k * chunk_tiles, (k + 1) * chunk_tiles), i.e. the entries
 // from k * chunk_tiles * kTileEntries on.  A run holds the chunk's entries of
-// the bin and one marker for every value of the high source bits in the
-// chunk's row range.  Entries with a column id outside [0, n) are not counted
+// the bin and the markers of the values of the high source bits (prev, end]
+// (see chunk_hi).  Entries with a column id outside [0, n) are not counted
 // (and not placed by the fill pass).
 __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, const int *__restrict__ col,
                                                            const Tile *__restrict__ tiles, int ntiles, BinDiv bd,
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
     }
     __syncthreads();
     const ChunkHi ch = chunk_hi(tiles, ntiles, k, chunk_tiles);
-    const int markers = ch.end - ch.lo + 1;
+    const int markers = ch.end - ch.prev;
     for (int b = tid; b < nbins; b += kBinThreads) cnt[(int64_t)b * nchunks + k] = hist[b] + markers;
     if (k == 0 && tid == 0) cnt[(int64_t)nbins * nchunks] = 0;  // becomes the total after the scan
 }
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
 // Before the first record with high source bits h, every bin's run gets the
 // marker of h, and of every value between the last one and h (values without
 // entries included, so that each run holds the count pass's number of
-// records).  A round whose rows share one value of the high bits (all but a
+// records); the first one is the value after the previous chunk's last.  A round whose rows share one value of the high bits (all but a
 // few rounds) is sorted once; one whose rows cross a boundary is processed
 // once per value in its row range, in ascending order.  Writes at or beyond
 // cap (only a malformed row_ptr gets there) are dropped.
@@ -146,7 +150,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
     const int b0 = tid * per, b1 = min(b0 + per, nbins);
     for (int b = b0; b < b1; ++b) hist[b] = 0;
     // markers are in place for every value up to hi_done (the same in every thread)
-    int hi_done = ch.lo - 1;
+    int hi_done = ch.prev;
     // markers of (hi_done, h] at the cursors of this thread's bins
     auto put_markers = [&](int h) {
         for (int b = b0; b < b1; ++b) {
@@ -344,13 +348,14 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
 // every wave rebuilds the full sources of its records from the checkpoint at
 // its first record and the markers among them.  All bins are launched at
 // once; the device starts later bins as earlier ones finish.
+template <int kPerLaneSpan>
 __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, int cap, const int *__restrict__ off,
                                                    const unsigned *__restrict__ brec, const int *__restrict__ bck,
                                                    const int *__restrict__ F, int *__restrict__ Fn,
                                                    const int *__restrict__ G, int *__restrict__ M) {
     __shared__ int wmin[kBinRowsMax];
-    constexpr int kSpan = kWave * kBinSpan;
-    static_assert(kSpan == 1 << kBinCkShift, "every wave starts at a checkpoint");
+    constexpr int kSpan = kWave * kPerLaneSpan;
+    static_assert(kSpan % (1 << kBinCkShift) == 0, "every wave starts at a checkpoint");
     constexpr int kWaves = 1024 / kWave;
     const int tid = threadIdx.x;
     const int lane = lane_id(), wave = tid / kWave;
@@ -365,15 +370,15 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, in
     for (int blk = p0 & ~(kSpan - 1); blk < p1; blk += kWaves * kSpan) {
         const int base = blk + wave * kSpan;
         if (base < p1) {
-            unsigned rec[kBinSpan];
+            unsigned rec[kPerLaneSpan];
             if (base >= p0 && base + kSpan <= p1) {
 #pragma unroll
-                for (int x = 0; x < kBinSpan; ++x) rec[x] = __builtin_nontemporal_load(brec + base + x * kWave + lane);
+                for (int x = 0; x < kPerLaneSpan; ++x) rec[x] = __builtin_nontemporal_load(brec + base + x * kWave + lane);
             } else {
                 // positions outside the bin read as markers; the bin's first
                 // record is a marker, which replaces what they carry
 #pragma unroll
-                for (int x = 0; x < kBinSpan; ++x) {
+                for (int x = 0; x < kPerLaneSpan; ++x) {
                     const int q = base + x * kWave + lane;
                     const unsigned r = __builtin_nontemporal_load(brec + min(max(q, p0), p1 - 1));
                     rec[x] = q >= p0 && q < p1 ? r : kBinMarker;
@@ -381,28 +386,30 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, in
             }
             // high bits in force before the wave's first record
             int carry = base >= p0 ? bck[base >> kBinCkShift] : 0;
-            int v[kBinSpan], d[kBinSpan];
+            int v[kPerLaneSpan], d[kPerLaneSpan];
 #pragma unroll
-            for (int x = 0; x < kBinSpan; ++x) {
+            for (int x = 0; x < kPerLaneSpan; ++x) {
                 const unsigned r = rec[x];
                 const bool mk = (r & 0xFFFFu) == kBinMarker;
                 const unsigned long long mm = __ballot(mk);
                 const int lo = (int)(r >> kSrcLoBits);
                 // the last marker at or before this lane, else the carry
-                const unsigned long long le = mm & upto;
-                const int from = le ? kWave - 1 - __clzll(le) : lane;
-                const int hb = __builtin_amdgcn_ds_bpermute(from << 2, lo);
-                const int hi = le ? hb : carry;
-                const int lv = __builtin_amdgcn_readlane(lo, mm ? kWave - 1 - __clzll(mm) : 0);
-                carry = mm ? lv : carry;
+                int hi = carry;
+                if (mm) {  // (uniform: most groups hold no marker)
+                    const unsigned long long le = mm & upto;
+                    const int from = le ? kWave - 1 - __clzll(le) : lane;
+                    const int hb = __builtin_amdgcn_ds_bpermute(from << 2, lo);
+                    hi = le ? hb : carry;
+                    carry = __builtin_amdgcn_readlane(lo, kWave - 1 - __clzll(mm));
+                }
                 const int dd = (int)(r & 0xFFFFu);
                 d[x] = mk || dd >= rows ? -1 : dd;  // (a row offset beyond the bin is never written)
                 v[x] = mk ? 0 : (int)min(((unsigned)hi << kSrcLoBits) | (unsigned)lo, (unsigned)(n - 1));
             }
 #pragma unroll
-            for (int x = 0; x < kBinSpan; ++x) v[x] = G[v[x]];
+            for (int x = 0; x < kPerLaneSpan; ++x) v[x] = G[v[x]];
 #pragma unroll
-            for (int x = 0; x < kBinSpan; ++x)
+            for (int x = 0; x < kPerLaneSpan; ++x)
                 if (d[x] >= 0) atomicMin(&wmin[d[x]], v[x]);
         }
         __syncthreads();

@@ -87,7 +87,9 @@ constexpr int kBinShiftMax = 15;        // largest power-of-two bin width that m
 constexpr int kBinShiftMin = 8;
 constexpr int kBinRowsMax = 40960;      // widest bin: a 160 KB LDS window in the dense pass
 constexpr int kNumCUs = 256;            // MI355X compute units: one dense-pass workgroup each at a time
-constexpr int kBinSpan = 32;            // entries per lane and step of the binned dense pass
+constexpr int kBinSpan = 16;            // entries per lane and step of the binned dense pass
+constexpr int kBinSpanWide = 32;        // the same for bins of at least kBinWideMin records
+constexpr int64_t kBinWideMin = 1 << 18; // (a wide step leaves a longer ragged last step per bin)
 constexpr int kBinThreads = 256;        // layout count pass
 constexpr int kFillThreads = 512;       // layout fill: one tile per wave and round
 constexpr int64_t kBinMaxCounts = 1 << 27;  // (bin, chunk) counters of the layout build
@@ -108,14 +110,14 @@ constexpr int kBinAutoMinN = 1 << 22;   // automatic mode: graphs with more vert
 // One 32-bit record per layout entry: the low kSrcLoBits bits of the source
 // above the row offset inside the bin.  The high bits of the source are
 // carried by marker records (row offset kBinMarker, high bits above it) that
-// open every (bin, chunk) run and every new value of the high bits inside it;
-// a bin's sources ascend, so a record takes the high bits of the last marker
-// before it.  kBinCkShift: the high bits in force at every position that is a
+// precede the first record of every new value of the high bits along a bin
+// (a bin opens with the marker of 0); a bin's sources ascend, so a record
+// takes the high bits of the last marker before it.  kBinCkShift: the high bits in force at every position that is a
 // multiple of 2^kBinCkShift are also stored in a checkpoint array, where a
 // wave of the dense pass starts.
 constexpr int kSrcLoBits = 16;
 constexpr unsigned kBinMarker = 0xFFFFu;
-constexpr int kBinCkShift = 11;
+constexpr int kBinCkShift = 10;
 static_assert(kBinRowsMax < (int)kBinMarker, "a row offset never equals the marker tag");
 
 // A graph entering or leaving the serving pool (see server.hip).

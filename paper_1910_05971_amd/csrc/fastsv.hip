@@ -159,14 +159,14 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
         L.chunk_tiles = (int)ct;
         L.nchunks = (int)((L.ntiles + ct - 1) / ct);
         L.bin_scan_len = nb * L.nchunks + 1;
-        // markers: per bin, one per chunk and one per boundary of the high
-        // source bits inside a chunk's rows; the chunks' row ranges follow
-        // each other, so the boundaries are at most (n - 1) >> kSrcLoBits
-        const int64_t markers = nb * (L.nchunks + ((n - 1) >> kSrcLoBits));
+        // markers: per bin, one per value of the high source bits, at most
+        // ((n - 1) >> kSrcLoBits) + 1 (a malformed row_ptr may ask for more;
+        // the fill drops writes beyond the capacity)
+        const int64_t markers = nb * (((n - 1) >> kSrcLoBits) + 1);
         const int64_t cap = nnz + markers;
         // positions are int; the automatic mode also skips graphs so sparse
         // that markers would be more than a quarter of the records
-        if (cap + (int64_t)kBinSpan * 1024 >= INT32_MAX || (lo.bin_mode == -1 && 4 * markers > nnz)) {
+        if (cap + (int64_t)kBinSpanWide * 1024 >= INT32_MAX || (lo.bin_mode == -1 && 4 * markers > nnz)) {
             L.bin = false;
             L.nbins = L.nchunks = 0;
         } else {
@@ -740,9 +740,19 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
                 if (stats) stats->blocked_iterations++;
             } else if (bin_state == 1) {
-                hipLaunchKernelGGL(k_bin_pull, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows, L.nchunks,
-                                   L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M);
-                if (stats) stats->binned_iterations++;
+                // wide steps only where bins are long enough that the ragged
+                // last step of each bin is a small share
+                const bool wide = L.bin_cap / L.nbins >= kBinWideMin;
+                if (wide)
+                    hipLaunchKernelGGL(k_bin_pull<kBinSpanWide>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
+                                       L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M);
+                else
+                    hipLaunchKernelGGL(k_bin_pull<kBinSpan>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
+                                       L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M);
+                if (stats) {
+                    stats->binned_iterations++;
+                    stats->bin_span = wide ? kBinSpanWide : kBinSpan;
+                }
             } else {
                 launch_dense(stream, base ? kDenseBaseGather : kDenseGather, w.tiles, (int)ntiles, P.rp, P.col,
                              P.vbase, F, Fn, G, w.M);

@@ -57,13 +57,13 @@ def test_defaults_and_sizes():
     for n, nnz in ((0, 0), (1, 0), (5, 8), (1000, 1), (3_000_000, 6668), (1 << 24, 536_865_336)):
         plain = binding.workspace_bytes(n, nnz, unbinned)
         assert plain > 0 and binding.workspace_bytes(n, nnz, binned) >= plain + (4 * nnz if nnz else 0)
-    # R-MAT scale 24: 512 bins, 16,384 chunks, at most 512 * (16,384 + 255)
-    # markers, under 2% of the entries
+    # R-MAT scale 24: 512 bins, at most 512 * 256 markers (one per value of
+    # the high 16 source bits and bin)
     n, nnz = 1 << 24, 536_865_336
     extra = binding.workspace_bytes(n, nnz, binned) - binding.workspace_bytes(n, nnz, unbinned)
-    assert 4 * nnz < extra < 4.2 * nnz
+    assert 4 * nnz < extra < 4.1 * nnz  # (with the (bin, chunk) counts, 33.5 MB)
     # the automatic mode leaves out graphs so sparse that markers would exceed
-    # a quarter of the entries (2^23 vertices: 256 bins, 127 boundaries)
+    # a quarter of the entries (2^23 vertices: 256 bins * 128 values)
     auto = binding.default_opts()
     assert binding.workspace_bytes(1 << 23, 100_000, auto) == binding.workspace_bytes(1 << 23, 100_000, unbinned)
     assert binding.workspace_bytes(1 << 23, 16 << 20, auto) > binding.workspace_bytes(1 << 23, 16 << 20, unbinned)
