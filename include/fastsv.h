@@ -79,11 +79,14 @@ typedef struct {
                                widened so that there are at most 64 blocks).  4..30 otherwise, and
                                the graph must then have at most 64 blocks. */
     int32_t binned;         /* binned dense SpMV: the stored entries are regrouped once per call
-                               by bins of consecutive vertices of their column (6 B per entry), and
-                               each dense iteration from the second on reduces a bin in LDS while
-                               gathering gf in ascending order.  1 use it, 0 never, -1 automatic
-                               (the default: graphs with more than 2^22 vertices).  Same iterates
-                               either way; not used when the graph needs more than 2048 bins. */
+                               by bins of consecutive vertices of their column (a 4-byte record per
+                               entry, plus at most ((n-1) >> 16) + 1 per bin for the high bits of
+                               the sources), and each dense iteration from the second on reduces
+                               a bin in LDS while gathering gf in ascending order.  1 use it, 0
+                               never, -1 automatic (the default: graphs with more than 2^22
+                               vertices whose entries are at least 4 times those extra records).
+                               Same iterates either way; not used when the graph needs more than
+                               2048 bins. */
     int32_t bin_shift;      /* bin width 2^bin_shift vertices, 8..15; 0 = automatic: the fewest
                                bins that are a multiple of 256 (the CU count) with at most 40960
                                vertices each (the dense pass's 160 KB LDS window) */
@@ -149,9 +152,10 @@ const char *fastsv_strerror(int status);
  * Workspace bytes needed by fastsv_cc_csr for a graph with n vertices and nnz
  * stored entries: five int32[n] vectors (two parent buffers of the Jacobi
  * pair, the MIN-accumulated mngf, the frontier list and its edge offsets),
- * the dense kernel's tile table and counters.  With blocked = 1 the
- * column-blocked copy of the matrix is added (about 3 int32 per stored entry).
- * Returns 0 for invalid sizes.
+ * the dense kernel's tile table and counters, and for graphs with more than
+ * 2^22 vertices the binned layout (about 4 B per stored entry; see
+ * fastsv_opts.binned).  With blocked = 1 the column-blocked copy of the matrix
+ * is added (about 3 int32 per stored entry).  Returns 0 for invalid sizes.
  */
 size_t fastsv_workspace_bytes(int32_t n, int64_t nnz);
 
