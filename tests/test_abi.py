@@ -67,6 +67,13 @@ def test_defaults_and_sizes():
     auto = binding.default_opts()
     assert binding.workspace_bytes(1 << 23, 100_000, auto) == binding.workspace_bytes(1 << 23, 100_000, unbinned)
     assert binding.workspace_bytes(1 << 23, 16 << 20, auto) > binding.workspace_bytes(1 << 23, 16 << 20, unbinned)
+    # layout positions are int32: records, markers (512 * 256 at 2^24
+    # vertices) and one wide step of slack must stay below 2^31, else the
+    # layout is left out even when forced
+    near = 2 ** 31 - 150_000
+    assert binding.workspace_bytes(1 << 24, near, binned) == binding.workspace_bytes(1 << 24, near, unbinned)
+    fits = 2 ** 31 - 300_000
+    assert binding.workspace_bytes(1 << 24, fits, binned) > binding.workspace_bytes(1 << 24, fits, unbinned) + 4 * fits
     lib = binding.load_library()
     assert lib.fastsv_strerror(0) == b"ok"
     assert b"max_iters" in lib.fastsv_strerror(-6)
