@@ -17,8 +17,8 @@
  * Contents
  *   oracle_uf_labels      union-find; plain definition of the result
  *   oracle_bfs_labels     BFS from each smallest unlabelled vertex (brute force)
- *   oracle_fastsv_alg2    Algorithm 2 (FastSV) step by step, Jacobi f / f_next
- *   oracle_fastsv_alg3    Algorithm 3 (FastSV in GraphBLAS) call by call
+ *   oracle_fastsv_alg2    FastSV (Algorithm 2), Jacobi f / f_next
+ *   oracle_fastsv_alg3    FastSV in the linear-algebra form of Algorithm 3
  *   oracle_sv_alg1        Algorithm 1 (simplified SV)
  *   oracle_sv_variant     Alg. 1 plus any subset of the Sec. 3 optimisations
  *   oracle_fastsv_async   Algorithm 2 with one vector read and written in place
@@ -112,17 +112,20 @@ int32_t oracle_bfs_labels(int32_t n, const int32_t *row_ptr, const int32_t *col,
 }
 
 /* ------------------------------------------------------------------------
- * O3: Algorithm 2 (FastSV), Sec. 3.
- *   init:   f[u] = f_next[u] = u                                  (Alg. 2 init)
- *   step 1: stochastic hooking  f_next[f[u]] <-min f[f[v]]  for (u,v) in E  (Sec. 3.2)
- *   step 2: aggressive hooking  f_next[u]    <-min f[f[v]]  for (u,v) in E  (Sec. 3.3)
- *   step 3: shortcutting        f_next[u]    <-min f[f[u]]  for u in V
- *   f <- f_next (a copy: both vectors hold the same values afterwards)
- *   until f[f] is unchanged (early termination, Sec. 3.4): the grandparent
- *   vector after the iteration is compared with the one before it, the first
- *   "before" being f[f] of the initial f, i.e. iota.
- * All reads in steps 1-3 see f as it was at the start of the iteration; all
- * writes go to f_next (Sec. 2.4, deterministic Jacobi form).
+ * O3: FastSV as Algorithm 2 states it (Sec. 3).
+ * Start from n single-vertex trees, f = iota, and a write vector f_next that
+ * holds the same values.  An iteration reads only the f it started with and
+ * lowers entries of f_next by min-updates (Sec. 2.4: separate read and write
+ * vectors make every iterate deterministic), in the paper's order:
+ *   - for each stored entry (u,v), the parent f[u] of u is offered v's
+ *     grandparent f[f[v]]: the tree containing u, or a part of it, hooks
+ *     onto v's tree without any root test (Sec. 3.1 and 3.2);
+ *   - for each stored entry (u,v), u itself is offered f[f[v]] (Sec. 3.3);
+ *   - every vertex is offered its own grandparent f[f[u]] (shortcutting).
+ * f then takes the values of f_next.  The loop ends after the first
+ * iteration that leaves the grandparent vector f[f] unchanged (Sec. 3.4,
+ * justified in Appendix A); the grandparent vector before the first
+ * iteration is that of the initial f, i.e. iota.
  * ------------------------------------------------------------------------ */
 int32_t oracle_fastsv_alg2(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t max_iters,
                            int32_t *f_out, int32_t *f_trace, int64_t *changed_trace, int32_t trace_cap) {
@@ -135,24 +138,24 @@ int32_t oracle_fastsv_alg2(int32_t n, const int32_t *row_ptr, const int32_t *col
     for (int32_t u = 0; u < n; ++u) gprev[u] = f[f[u]];
     int32_t it = 0;
     for (;;) {
-        /* step 1: stochastic hooking */
+        /* hooking of f[u] onto v's grandparent (stochastic, Sec. 3.2) */
         for (int32_t u = 0; u < n; ++u)
             for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
                 int32_t v = col[e];
                 fn[f[u]] = min32(fn[f[u]], f[f[v]]);
             }
-        /* step 2: aggressive hooking */
+        /* hooking of u itself onto v's grandparent (aggressive, Sec. 3.3) */
         for (int32_t u = 0; u < n; ++u)
             for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
                 int32_t v = col[e];
                 fn[u] = min32(fn[u], f[f[v]]);
             }
-        /* step 3: shortcutting */
+        /* shortcutting onto the own grandparent */
         for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);
-        /* f <- f_next */
+        /* the next iteration reads what was written */
         memcpy(f, fn, (size_t)n * sizeof(int32_t));
         ++it;
-        /* termination test on the grandparent vector */
+        /* did any grandparent change? (Sec. 3.4) */
         int64_t changed = 0;
         for (int32_t u = 0; u < n; ++u) {
             int32_t g = f[f[u]];
@@ -169,22 +172,25 @@ int32_t oracle_fastsv_alg2(int32_t n, const int32_t *row_ptr, const int32_t *col
 }
 
 /* ------------------------------------------------------------------------
- * O4: Algorithm 3 (FastSV expressed with GraphBLAS calls), Sec. 4.1.
- * Each call is written out on dense vectors:
- *   gf = dup(f); dup = dup(gf); mngf = dup(gf); value = f (extractTuples)
- *   repeat
- *     mxv(mngf, MIN, (select2nd,min), A, gf):
- *         t[i] = min over stored A(i,j) of gf[j]  (absent for an empty row);
- *         mngf[i] = min(mngf[i], t[i])
- *     assign(f, MIN, mngf, value):      f[value[i]] = min(f[value[i]], mngf[i])
- *     eWiseMult(f, MIN, f, mngf):       f[i] = min(f[i], mngf[i])
- *     eWiseMult(f, MIN, f, gf):         f[i] = min(f[i], gf[i])
- *     extractTuples(value, f):          value = f
- *     extract(gf, f, value):            gf[i] = f[value[i]]
- *     eWiseMult(diff, ISNE, dup, gf); reduce(sum, +, diff)
- *     assign(dup, gf)   (the listing prints "gp"; it is the vector gf)
- *   until sum == 0
- * `f_init` (may be NULL for iota) is the input parent vector of Alg. 3.
+ * O4: FastSV in the linear-algebra form of Sec. 4.1 (Algorithm 3), on dense
+ * vectors.  State: the parent vector f (the input f_init, or iota), the
+ * grandparent vector gf, its copy from the previous iteration (dup), the
+ * neighbour minimum mngf and value, the parents as they were when gf was
+ * last formed.  The algorithm initialises gf, dup and mngf with f itself.
+ * One iteration:
+ *   - mngf[i] is lowered to the smallest gf[j] over the stored entries (i,j)
+ *     of row i: the matrix-vector product over the (select2nd, min)
+ *     semiring, accumulated with MIN into the mngf kept from before; an
+ *     empty row leaves mngf[i] as it is;
+ *   - f[value[i]] is lowered to mngf[i] (stochastic hooking as an assign
+ *     with a MIN accumulator; the target is the parent of i from the start
+ *     of the iteration);
+ *   - f[i] is lowered to mngf[i] (aggressive hooking) and to gf[i]
+ *     (shortcutting), both element-wise minima;
+ *   - value takes the new f, and gf[i] = f[value[i]] is the new grandparent;
+ *   - the number of entries in which gf differs from dup is the termination
+ *     count; dup then takes gf (the whole vector).
+ * The loop ends when that count is zero.
  * ------------------------------------------------------------------------ */
 int32_t oracle_fastsv_alg3(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t max_iters,
                            const int32_t *f_init, int32_t *f_out, int32_t *f_trace,
@@ -203,7 +209,7 @@ int32_t oracle_fastsv_alg3(int32_t n, const int32_t *row_ptr, const int32_t *col
     memcpy(value, f, (size_t)n * sizeof(int32_t));
     int32_t it = 0;
     for (;;) {
-        /* Step 1: stochastic hooking = mxv then assign */
+        /* neighbour minimum of the grandparents, then the hook of each parent */
         for (int32_t i = 0; i < n; ++i) {
             if (row_ptr[i + 1] == row_ptr[i]) continue;
             int32_t t = gf[col[row_ptr[i]]];
@@ -211,14 +217,14 @@ int32_t oracle_fastsv_alg3(int32_t n, const int32_t *row_ptr, const int32_t *col
             mngf[i] = min32(mngf[i], t);
         }
         for (int32_t i = 0; i < n; ++i) f[value[i]] = min32(f[value[i]], mngf[i]);
-        /* Step 2: aggressive hooking */
+        /* each vertex onto its neighbour minimum */
         for (int32_t i = 0; i < n; ++i) f[i] = min32(f[i], mngf[i]);
-        /* Step 3: shortcutting */
+        /* each vertex onto its grandparent */
         for (int32_t i = 0; i < n; ++i) f[i] = min32(f[i], gf[i]);
-        /* Step 4: grandparents */
+        /* the new grandparents */
         memcpy(value, f, (size_t)n * sizeof(int32_t));
         for (int32_t i = 0; i < n; ++i) gf[i] = f[value[i]];
-        /* Step 5: termination */
+        /* count the grandparents that changed, and remember them */
         int64_t sum = 0;
         for (int32_t i = 0; i < n; ++i) sum += (dup[i] != gf[i]);
         memcpy(dup, gf, (size_t)n * sizeof(int32_t));
@@ -245,12 +251,22 @@ int32_t oracle_fastsv_alg3(int32_t n, const int32_t *row_ptr, const int32_t *col
  *      of when f is unchanged
  * flags = 0 is Alg. 1; flags = 15 is Alg. 2.
  *
- * Without bit 2 the iteration is Alg. 1's two phases: conditional hooking
- * (only when f[u] is a root and the hook value is smaller than f[u]) into
- * f_next, f <- f_next, then shortcutting f_next[u] <- f[f[u]] where f[u] is
- * not a root, f <- f_next.  Several edges may hook the same root in one
- * phase; the writes are resolved by taking the minimum, which keeps the
- * iterates deterministic (Sec. 2.4 and the MIN accumulator of Sec. 4.1).
+ * Without bit 2 the iteration is Alg. 1's two phases.  First, conditional
+ * hooking into f_next: for a stored entry (u,v), if f[u] is a root
+ * (f[u] == f[f[u]]) and v's parent is smaller than it (f[v] < f[u]), f[u] is
+ * hooked onto v's parent, or with bit 1 onto v's grandparent f[f[v]].
+ * Sec. 3.1 changes only the vertex hooked onto and keeps the condition on
+ * f[v]; since f[f[v]] <= f[v], the hook still lowers f[u].  Several edges
+ * may hook the same root in one phase; the writes are resolved by taking the
+ * minimum, which keeps the iterates deterministic (Sec. 2.4 and the MIN
+ * accumulator of Sec. 4.1).  With bit 4 every u is also lowered to the
+ * smallest such value over all of its entries, unconditionally (Sec. 3.3).
+ * f <- f_next.  Second, shortcutting: f_next[u] <- f[f[u]] where f[u] is not
+ * a root; f <- f_next.
+ * With bit 2 the root test goes (Sec. 3.2), and the updates are Alg. 2's
+ * min-assignments: removing the root test turns the hook into Alg. 2's
+ * stochastic hook, and sv4 then differs from Alg. 2 only in its termination
+ * test (Sec. 5.2 reports that early termination removes one iteration).
  * Termination without bit 8: f after the iteration equals f before it.
  * ------------------------------------------------------------------------ */
 int32_t oracle_sv_variant(int32_t n, const int32_t *row_ptr, const int32_t *col, int32_t flags,
@@ -289,7 +305,7 @@ int32_t oracle_sv_variant(int32_t n, const int32_t *row_ptr, const int32_t *col,
                 for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
                     int32_t v = col[e];
                     int32_t h = grand ? f[f[v]] : f[v];
-                    if (f[u] == f[f[u]] && h < f[u]) fn[f[u]] = min32(fn[f[u]], h);
+                    if (f[u] == f[f[u]] && f[v] < f[u]) fn[f[u]] = min32(fn[f[u]], h);
                 }
             if (aggr)
                 for (int32_t u = 0; u < n; ++u)

@@ -509,6 +509,7 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
     it = 0;
     const dim3 grid(grid_for(ntiles, kHookWaves)), block(kWave * kHookWaves);
     const dim3 vgrid(grid_for(n, 256, 65536)), vblock(256);
+    const dim3 rgrid(grid_for(n, 256 / kWave, 8192));  // k_var_root_hook: one wave per row
     for (;;) {
         ++it;
         int *F = w.F[(it + 1) & 1];
@@ -519,9 +520,14 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
         const int ti = it - 1;
         const bool timed = opts.timing && ti < FASTSV_TRACE_ITERS;
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
-        if (ntiles > 0)
-            hipLaunchKernelGGL((k_tile_reduce<kVariant>), grid, block, 0, stream, w.tiles, (int)ntiles, P.rp, P.col,
-                               grand ? G : F, F, Fn, G, w.M, fl);
+        if (ntiles > 0) {
+            if (grand && !stoch)
+                hipLaunchKernelGGL(k_var_root_hook, rgrid, dim3(256), 0, stream, n, P.rp, P.col, F, G, Fn,
+                                   (fl & 4) ? 1 : 0);
+            else
+                hipLaunchKernelGGL((k_tile_reduce<kVariant>), grid, block, 0, stream, w.tiles, (int)ntiles, P.rp,
+                                   P.col, grand ? G : F, F, Fn, G, w.M, fl);
+        }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
         launch_zero_iter(stream, ic);
         if (!stoch) hipLaunchKernelGGL(k_var_shortcut, vgrid, vblock, 0, stream, n, Fn, T);

@@ -218,9 +218,11 @@ enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kPhase
 //     (the shortcut); Fn[f[u]] <-min m with no root test, plus, when
 //     aggressive (Sec. 3.3), Fn[u] <-min m.  Both are no-ops unless m < gf[u]
 //     (the write buffer starts at or below gf[u] at both targets).
-//   otherwise (Alg. 1's first phase, write buffer = copy of f): a root f[u]
-//     (f[u] = gf[u]) is hooked, Fn[f[u]] <-min m, when m < f[u]; aggressive
-//     hooking adds Fn[u] <-min m.
+//   otherwise, without grandparent hooking (Alg. 1's first phase, write
+//     buffer = copy of f): a root f[u] (f[u] = gf[u]) is hooked onto the
+//     smallest f[v] below it, which is m whenever m < f[u]; aggressive hooking
+//     adds Fn[u] <-min m.  (With grandparent hooking the hook condition tests
+//     f[v], not the value hooked onto: k_var_root_hook.)
 __device__ __forceinline__ void finish_variant(int u, int m, int flags, const int *__restrict__ F,
                                                int *__restrict__ Fn, const int *__restrict__ G) {
     const bool stoch = flags & 2, aggr = flags & 4;
@@ -1041,6 +1043,42 @@ __global__ void k_var_shortcut(int n, const int *__restrict__ Fn, int *__restric
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int stride = gridDim.x * blockDim.x;
     for (int u = i; u < n; u += stride) T[u] = Fn[Fn[u]];
+}
+
+// Alg. 1's hooking phase with grandparent hooking and no stochastic hooking
+// (Sec. 3.1: the hook still requires f[u] to be a root and f[v] < f[u]; only
+// the vertex hooked onto changes, from f[v] to f[f[v]]).  One wave per row,
+// rows dealt grid-stride: the lanes stride over the row's entries and keep
+//   mc = min gf[v] over the entries with f[v] < f[u]   (the root hook)
+//   ma = min gf[v] over all entries                     (aggressive hooking)
+// then Fn[f[u]] <-min mc if f[u] is a root, and Fn[u] <-min ma if aggressive.
+// Fn starts as a copy of f; f[f[v]] <= f[v] < f[u], so a root hook always
+// lowers its target.
+__global__ __launch_bounds__(256) void k_var_root_hook(int n, const int *__restrict__ rp,
+                                                       const int *__restrict__ col, const int *__restrict__ F,
+                                                       const int *__restrict__ G, int *__restrict__ Fn, int aggr) {
+    const int lane = lane_id();
+    const int waves = gridDim.x * (blockDim.x / kWave);
+    for (int u = blockIdx.x * (blockDim.x / kWave) + (int)threadIdx.x / kWave; u < n; u += waves) {
+        const int fu = F[u];
+        const int e1 = rp[u + 1];
+        int mc = INT_MAX, ma = INT_MAX;
+        for (int e = rp[u] + lane; e < e1; e += kWave) {
+            const int v = col[e];
+            const int gv = G[v];
+            ma = min(ma, gv);
+            if (F[v] < fu) mc = min(mc, gv);
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) {
+            mc = min(mc, __shfl_xor(mc, d, kWave));
+            ma = min(ma, __shfl_xor(ma, d, kWave));
+        }
+        if (lane == 0) {
+            if (mc < fu && fu == G[u]) atomicMin(Fn + fu, mc);
+            if (aggr && ma < fu) atomicMin(Fn + u, ma);
+        }
+    }
 }
 
 __global__ void k_var_finish(int n, const int *__restrict__ fk, int *__restrict__ Fn, int *__restrict__ F,

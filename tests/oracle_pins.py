@@ -153,7 +153,9 @@ def pin_path_closed_form(orc, sizes=(1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 33,
 
 
 def pin_golden(orc):
-    """Hand-worked trajectories stored under tests/golden/."""
+    """Hand-worked trajectories stored under tests/golden/: Algorithm 2's (run
+    through Alg. 2, Alg. 3 and the sv5 variant) and, where a file lists them,
+    those of the convergence-ablation variants sv1..sv4."""
     for fname in sorted(os.listdir(GOLDEN)):
         if not fname.endswith(".json"):
             continue
@@ -161,12 +163,107 @@ def pin_golden(orc):
             ex = json.load(fh)
         n = ex["n"]
         rp, col = csr_from_pairs(n, ex["edges"])
-        for name, r in (("alg2", orc.fastsv_alg2(n, rp, col, CAP, trace_cap=32)),
-                        ("alg3", orc.fastsv_alg3(n, rp, col, CAP, trace_cap=32)),
-                        ("sv5", orc.sv_variant(n, rp, col, O.SV_FLAGS["sv5"], CAP, trace_cap=32))):
-            assert r.iterations == ex["iterations"], f"{fname} {name}: iterations {r.iterations}"
-            assert r.trace.tolist() == ex["trajectory"], f"{fname} {name}: trajectory {r.trace.tolist()}"
-            assert r.changed.tolist() == ex["changed"], f"{fname} {name}: changed {r.changed.tolist()}"
+        if "trajectory" in ex:
+            for name, r in (("alg2", orc.fastsv_alg2(n, rp, col, CAP, trace_cap=32)),
+                            ("alg3", orc.fastsv_alg3(n, rp, col, CAP, trace_cap=32)),
+                            ("sv5", orc.sv_variant(n, rp, col, O.SV_FLAGS["sv5"], CAP, trace_cap=32))):
+                assert r.iterations == ex["iterations"], f"{fname} {name}: iterations {r.iterations}"
+                assert r.trace.tolist() == ex["trajectory"], f"{fname} {name}: trajectory {r.trace.tolist()}"
+                assert r.changed.tolist() == ex["changed"], f"{fname} {name}: changed {r.changed.tolist()}"
+        for name, v in ex.get("variants", {}).items():
+            assert v["flags"] == O.SV_FLAGS[name], f"{fname}: flags of {name}"
+            r = orc.sv_variant(n, rp, col, v["flags"], CAP, trace_cap=32)
+            assert r.iterations == v["iterations"], f"{fname} {name}: iterations {r.iterations}"
+            assert r.trace.tolist() == v["trajectory"], f"{fname} {name}: trajectory {r.trace.tolist()}"
+            assert r.changed.tolist() == v["changed"], f"{fname} {name}: changed {r.changed.tolist()}"
+
+
+def sv_path_closed_form(name, n, k):
+    """Sorted path 0-1-...-(n-1), iterate k >= 1 of an ablation variant.
+
+    sv1 and sv2 (Alg. 1, with or without grandparent hooking): in iteration 1
+    every root u > 0 hooks onto u-1 and then shortcuts to u-2, so
+    f_1[u] = max(0, u-2).  From then on a vertex whose parent is a root has
+    parent 0 and no smaller neighbour parent, so no hook fires and each
+    iteration is one pointer jump: f_k[u] = max(0, u - 2^k).
+    sv3 (stochastic hooking without aggressive hooking): with f = max(0, u-a),
+    the only vertex u whose parent is x > 0 is x + a; its neighbours' smallest
+    grandparent is max(0, x - 1 - a), and the shortcut offers max(0, x - 2a),
+    which is never larger for a >= 1.  From f_1[u] = max(0, u-1) this gives
+    f_k[u] = max(0, u - 2^(k-1)).
+    sv4 has Algorithm 2's iterates, f_k[u] = max(0, u - (2^k - 1)) (see
+    path_closed_form).
+    """
+    u = np.arange(n, dtype=np.int64)
+    a = {"sv1": 1 << k, "sv2": 1 << k, "sv3": 1 << (k - 1), "sv4": (1 << k) - 1}[name]
+    return np.maximum(0, u - a).astype(np.int32)
+
+
+def pin_sv_path_closed_form(orc, sizes=(1, 2, 3, 4, 5, 6, 9, 16, 17, 33, 100)):
+    """Trajectories and iteration counts of sv1..sv4 on the sorted path.  They
+    test f, so they stop at the first k with f_k = f_(k-1) (f_0 = iota)."""
+    for n in sizes:
+        rp, col = csr_from_pairs(n, [(u, u + 1) for u in range(n - 1)])
+        for name in ("sv1", "sv2", "sv3", "sv4"):
+            r = orc.sv_variant(n, rp, col, O.SV_FLAGS[name], CAP, trace_cap=64)
+            prev = np.arange(n, dtype=np.int32)
+            k = 0
+            while True:
+                k += 1
+                fk = sv_path_closed_form(name, n, k)
+                assert k <= r.iterations, f"path n={n} {name}: stopped after {r.iterations}, f_{k} still changes"
+                assert np.array_equal(r.trace[k - 1], fk), f"path n={n} {name}: f_{k} {r.trace[k - 1]} != {fk}"
+                assert r.changed[k - 1] == int(np.count_nonzero(fk != prev)), f"path n={n} {name}: changed[{k}]"
+                if np.array_equal(fk, prev):
+                    break
+                prev = fk
+            assert r.iterations == k, f"path n={n} {name}: {r.iterations} iterations, expected {k}"
+
+
+def pin_sv4_follows_alg2(orc, graphs=None):
+    """sv4 applies all three hooks of Algorithm 2 and tests f instead of f[f]
+    (Sec. 3.4): its iterates are Algorithm 2's, continued by one iterate that
+    Lemma T fixes (once f[f] is unchanged, f stays as it is), and it stops at
+    the first iterate equal to its predecessor.  sv5 is Algorithm 2 itself."""
+    for g in graphs or random_small_graphs():
+        r2 = orc.fastsv_alg2(g.n, g.row_ptr, g.col, CAP, trace_cap=256)
+        traj = list(r2.trace) + [r2.trace[-1]]  # Lemma T: the next iterate repeats
+        prev = np.arange(g.n, dtype=np.int32)
+        want_k = None
+        for k, fk in enumerate(traj, start=1):
+            if np.array_equal(fk, prev):
+                want_k = k
+                break
+            prev = fk
+        r4 = orc.sv_variant(g.n, g.row_ptr, g.col, O.SV_FLAGS["sv4"], CAP, trace_cap=256)
+        assert r4.iterations == want_k, f"{g.name}: sv4 {r4.iterations} iterations, expected {want_k}"
+        for k in range(want_k):
+            assert np.array_equal(r4.trace[k], traj[k]), f"{g.name}: sv4 f_{k + 1}"
+        r5 = orc.sv_variant(g.n, g.row_ptr, g.col, O.SV_FLAGS["sv5"], CAP, trace_cap=256)
+        assert r5.iterations == r2.iterations, g.name
+        assert np.array_equal(r5.trace, r2.trace) and np.array_equal(r5.changed, r2.changed), g.name
+
+
+def pin_sv_root_hooks_keep_trees(orc, graphs=None):
+    """Without stochastic hooking only roots are hooked (Alg. 1's test), so a
+    tree is never split: two vertices with the same parent after an iterate
+    keep a common root in every later iterate, and every hook lowers a root
+    by moving it into a tree with a smaller id (Sec. 2.4)."""
+    for g in graphs or random_small_graphs()[:4]:
+        for name in ("sv1", "sv2"):
+            r = orc.sv_variant(g.n, g.row_ptr, g.col, O.SV_FLAGS[name], CAP, trace_cap=256)
+            assert r.iterations > 0, (g.name, name)
+            steps = r.trace[:r.iterations]
+            for k in range(1, len(steps)):
+                a, b = steps[k - 1], steps[k]
+                root_a, root_b = a.copy(), b.copy()
+                for _ in range(24):  # pointer doubling: f^(2^24) reaches every root
+                    root_a, root_b = root_a[root_a], root_b[root_b]
+                # vertices in one tree of f_(k-1) share a tree of f_k
+                order = np.argsort(root_a, kind="stable")
+                ra, rb = root_a[order], root_b[order]
+                same = ra[1:] == ra[:-1]
+                assert np.all(rb[1:][same] == rb[:-1][same]), f"{g.name} {name}: a tree was split at {k + 1}"
 
 
 def pin_small_closed_forms(orc):
@@ -311,4 +408,4 @@ def pin_iteration_cap(orc):
 
 ALL_PINS = [pin_path_closed_form, pin_golden, pin_small_closed_forms, pin_known_components,
             pin_percolation_extremes, pin_scipy, pin_invariants, pin_early_termination,
-            pin_iteration_cap]
+            pin_iteration_cap, pin_sv_path_closed_form, pin_sv4_follows_alg2, pin_sv_root_hooks_keep_trees]

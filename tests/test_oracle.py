@@ -56,6 +56,18 @@ def test_iteration_cap(orc):
     P.pin_iteration_cap(orc)
 
 
+def test_sv_variants_path_closed_form(orc):
+    P.pin_sv_path_closed_form(orc)
+
+
+def test_sv4_follows_alg2(orc):
+    P.pin_sv4_follows_alg2(orc)
+
+
+def test_sv_root_hooks_keep_trees(orc):
+    P.pin_sv_root_hooks_keep_trees(orc)
+
+
 def test_empty_graph(orc):
     rp = np.zeros(1, dtype=np.int32)
     col = np.zeros(0, dtype=np.int32)

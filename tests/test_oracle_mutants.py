@@ -17,7 +17,7 @@ MUTANTS = {
     # Algorithm 2
     "alg2_drop_stochastic": ("fn[f[u]] = min32(fn[f[u]], f[f[v]]);", ";"),
     "alg2_drop_aggressive": ("fn[u] = min32(fn[u], f[f[v]]);", ";"),
-    "alg2_drop_shortcut": ("for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);\n        /* f <- f_next */", "/* f <- f_next */"),
+    "alg2_drop_shortcut": ("for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);\n        /* the next iteration", "/* the next iteration"),
     "alg2_hook_parent_not_grandparent": ("fn[f[u]] = min32(fn[f[u]], f[f[v]]);", "fn[f[u]] = min32(fn[f[u]], f[v]);"),
     "alg2_aggressive_parent_not_grandparent": ("fn[u] = min32(fn[u], f[f[v]]);", "fn[u] = min32(fn[u], f[v]);"),
     "alg2_stochastic_target_from_next": ("fn[f[u]] = min32(fn[f[u]], f[f[v]]);", "fn[fn[u]] = min32(fn[fn[u]], f[f[v]]);"),
@@ -25,7 +25,7 @@ MUTANTS = {
     # symmetric CSR holds both orientations of every edge)
     "alg2_stochastic_reads_u": ("fn[f[u]] = min32(fn[f[u]], f[f[v]]);", "fn[f[u]] = min32(fn[f[u]], f[f[u]]);"),
     "alg2_terminate_on_f": ("int32_t g = f[f[u]];\n            changed += (g != gprev[u]);", "int32_t g = f[u];\n            changed += (g != gprev[u]);"),
-    "alg2_shortcut_parent": ("for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);\n        /* f <- f_next */", "for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[u]);\n        /* f <- f_next */"),
+    "alg2_shortcut_parent": ("for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);\n        /* the next iteration", "for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[u]);\n        /* the next iteration"),
     # Algorithm 3
     # (indexing the assign by the partly updated f instead of value is an
     # equivalent mutant in increasing-i order: f[i] can only have been lowered
@@ -39,6 +39,19 @@ MUTANTS = {
                              "for (int32_t e = row_ptr[i] + 1; e < row_ptr[i + 1]; ++e) t = gf[col[e]];"),
     "alg3_extract_parent": ("for (int32_t i = 0; i < n; ++i) gf[i] = f[value[i]];", "for (int32_t i = 0; i < n; ++i) gf[i] = f[i];"),
     "alg3_dup_not_updated": ("memcpy(dup, gf, (size_t)n * sizeof(int32_t));\n        ++it;", "++it;"),
+    # convergence-ablation variants (Alg. 1 plus the changes of Sec. 3)
+    "sv_root_test_dropped": ("if (f[u] == f[f[u]] && f[v] < f[u]) fn[f[u]]", "if (f[v] < f[u]) fn[f[u]]"),
+    "sv_root_test_on_u": ("if (f[u] == f[f[u]] && f[v] < f[u]) fn[f[u]]", "if (f[u] == u && f[v] < f[u]) fn[f[u]]"),
+    "sv_hook_condition_on_grandparent": ("if (f[u] == f[f[u]] && f[v] < f[u]) fn[f[u]]", "if (f[u] == f[f[u]] && h < f[u]) fn[f[u]]"),
+    # (a non-strict f[v] <= f[u] is an equivalent mutant: with f[v] = f[u] a
+    # root, both f[v] and f[f[v]] equal f[u], which the root already holds)
+    "sv_grandparent_ignored": ("int32_t h = grand ? f[f[v]] : f[v];\n                    if (f[u] == f[f[u]]", "int32_t h = f[v];\n                    if (f[u] == f[f[u]]"),
+    "sv_hook_target_u": ("if (f[u] == f[f[u]] && f[v] < f[u]) fn[f[u]] = min32(fn[f[u]], h);", "if (f[u] == f[f[u]] && f[v] < f[u]) fn[u] = min32(fn[u], h);"),
+    "sv_shortcut_to_root_test_parent": ("if (f[u] != f[f[u]]) fn[u] = f[f[u]];", "if (f[u] != f[f[u]]) fn[u] = f[u];"),
+    "sv_stochastic_skips_shortcut": ("for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);\n            memcpy", "memcpy"),
+    "sv_stochastic_aggressive_always": ("                        fn[u] = min32(fn[u], h);\n                    }\n            for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);",
+                                        "                        fn[u] = min32(fn[u], h);\n                    }\n            for (int32_t u = 0; u < n; ++u) for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) fn[u] = min32(fn[u], f[f[col[e]]]);\n            for (int32_t u = 0; u < n; ++u) fn[u] = min32(fn[u], f[f[u]]);"),
+    "sv_termination_tests_f_when_early": ("int32_t x = early ? f[f[u]] : f[u];", "int32_t x = f[u];"),
     # union-find and BFS
     "uf_link_smaller_below_larger": ("if (a < b) labels[b] = a;\n            else if (b < a) labels[a] = b;\n        }\n    }",
                                      "if (a < b) labels[a] = b;\n            else if (b < a) labels[b] = a;\n        }\n    }"),
@@ -48,7 +61,8 @@ MUTANTS = {
 }
 
 PINS = [lambda o: P.pin_exhaustive(o, n=5), P.pin_path_closed_form, P.pin_golden,
-        P.pin_small_closed_forms, P.pin_known_components, P.pin_scipy, P.pin_invariants]
+        P.pin_small_closed_forms, P.pin_known_components, P.pin_scipy, P.pin_invariants,
+        P.pin_sv_path_closed_form, P.pin_sv4_follows_alg2, P.pin_sv_root_hooks_keep_trees]
 
 
 def _build_mutant(tmp_path, name, old, new):
