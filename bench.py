@@ -63,7 +63,12 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the convergence ablation, asynchronous mode and warm-start measurements")
-    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-requests", type=int, default=22100,
+                    help="requests in the serving trace; those arriving in the first --serve-warmup seconds are "
+                         "served but not counted")
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--serve-er-pool", type=int, default=1024)
+    ap.add_argument("--serve-rmat-pool", type=int, default=4)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="counter-measured HBM bytes per dense step (see profiles/)")
@@ -309,6 +314,31 @@ def bench_extras(fs, torch, np, c2, c2_labels):
     return out
 
 
+def host_info():
+    """The host the CPU oracle runs on: CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def oracle_workers():
+    """Threads for the oracle's all-core runs: the cores this process may use,
+    at most 16 (the GPU machine's CPU share).  ctypes releases the GIL during each
+    oracle call, so threads run the C oracle in parallel."""
+    return max(1, min(16, host_info()["usable_cores"]))
+
+
 def bench_batch(fs, torch, np):
     from paper_1910_05971_amd import graphgen as gg
     t0 = time.time()
@@ -322,10 +352,11 @@ def bench_batch(fs, torch, np):
     for _ in range(3):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, iters, st = fs.cc_batch_csr(vo, eo, rp, col)
+        labels, iters, st = fs.cc_batch_csr(vo, eo, rp, col)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
     t_batch = sorted(times)[1]
+    gpu_labels, gpu_iters = labels.cpu().numpy(), iters.cpu().numpy()
     # plain: one cc_csr call per graph on device-resident sub-CSRs
     subs = []
     for gi in range(b.num_graphs):
@@ -340,22 +371,60 @@ def bench_batch(fs, torch, np):
         fs.cc_csr(r, c)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t
-    return {"workload": "4096 Erdos-Renyi graphs, n log-uniform in [64, 65536), average degree uniform in [2, 32]",
-            "graphs": b.num_graphs, "total_edges_undirected": int(b.m_eff.sum()),
-            "graphs_per_s": b.num_graphs / t_batch, "ms_per_batch": 1000 * t_batch,
-            "iterations": st.iterations, "plain_graphs_per_s": b.num_graphs / t_plain,
-            "speedup_vs_plain": t_plain / t_batch}
+    del subs, vo, eo, rp, col, labels, iters
+    torch.cuda.empty_cache()
+    out = {"workload": "4096 Erdos-Renyi graphs, n log-uniform in [64, 65536), average degree uniform in [2, 32]",
+           "graphs": b.num_graphs, "total_edges_undirected": int(b.m_eff.sum()),
+           "graphs_per_s": b.num_graphs / t_batch, "ms_per_batch": 1000 * t_batch,
+           "iterations": st.iterations, "plain_graphs_per_s": b.num_graphs / t_plain,
+           "speedup_vs_plain": t_plain / t_batch}
+    return out, (b, gpu_labels, gpu_iters)
 
 
-def bench_serve(args, torch, np):
+def batch_oracle(np, b, gpu_labels, gpu_iters):
+    """CPU-baseline leg of the batch: union-find over all graphs on one core and
+    on all usable cores, and Algorithm 2 on all cores; each graph's batched
+    labels and iteration count are compared with them (outside any timed GPU
+    region)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    G = b.num_graphs
+    graphs = [b.graph(i) for i in range(G)]
+    t = time.perf_counter()
+    uf = [oracle.uf_labels(g.n, g.row_ptr, g.col) for g in graphs]
+    t_uf1 = time.perf_counter() - t
+    W = oracle_workers()
+    with ThreadPoolExecutor(W) as ex:
+        t = time.perf_counter()
+        list(ex.map(lambda g: oracle.uf_labels(g.n, g.row_ptr, g.col), graphs))
+        t_ufw = time.perf_counter() - t
+        t = time.perf_counter()
+        its = list(ex.map(lambda g: oracle.fastsv_alg2(g.n, g.row_ptr, g.col).iterations, graphs))
+        t_a2w = time.perf_counter() - t
+    lab_ok = all(np.array_equal(gpu_labels[b.vtx_off[i]:b.vtx_off[i + 1]], uf[i]) for i in range(G))
+    it_ok = bool(np.array_equal(np.asarray(its), gpu_iters[:G]))
+    return {"labels_match_oracle": bool(lab_ok), "iterations_match_oracle": it_ok,
+            "cpu_oracle": {"union_find_1core_graphs_per_s": G / t_uf1,
+                           "union_find_all_cores_graphs_per_s": G / t_ufw,
+                           "alg2_all_cores_graphs_per_s": G / t_a2w, "cores": W,
+                           "sample": f"all {G} graphs of the batch"}}
+
+
+def bench_serve(args, torch, np, want_check):
     from paper_1910_05971_amd import graphgen as gg, serving
     t0 = time.time()
-    tr = gg.request_trace(args.serve_requests, args.serve_rate)
+    tr = gg.request_trace(args.serve_requests, args.serve_rate, er_pool=args.serve_er_pool,
+                          rmat_pool=args.serve_rmat_pool)
     graphs = serving.pin_graphs(tr.graphs)
-    log(f"serving trace: {len(graphs)} requests ({int(tr.kinds.sum())} R-MAT scale 20) in {time.time() - t0:.1f}s")
-    out = {"workload": f"Poisson {args.serve_rate:.0f} req/s, {len(graphs)} requests: 99% Erdos-Renyi from the "
-                       f"batch distribution, 1% R-MAT scale 20 edge factor 16; host-resident page-locked CSRs",
-           "requests": len(graphs), "rmat_requests": int(tr.kinds.sum())}
+    measured = tr.arrivals >= args.serve_warmup
+    nmeas = int(measured.sum())
+    log(f"serving trace: {len(graphs)} requests ({int(tr.kinds.sum())} R-MAT scale 20), {nmeas} after the "
+        f"{args.serve_warmup:g} s warm-up, in {time.time() - t0:.1f}s")
+    out = {"workload": f"Poisson {args.serve_rate:.0f} req/s, {len(graphs)} requests ({nmeas} measured after a "
+                       f"{args.serve_warmup:g} s warm-up): 99% Erdos-Renyi from the batch distribution (pool of "
+                       f"{args.serve_er_pool} graphs), 1% R-MAT scale 20 edge factor 16 (pool of "
+                       f"{args.serve_rmat_pool}); host-resident page-locked CSRs",
+           "requests": len(graphs), "measured_requests": nmeas, "rmat_requests": int(tr.kinds.sum())}
 
     def pct(lat):
         return float(np.percentile(lat, 50) * 1e3), float(np.percentile(lat, 99) * 1e3)
@@ -369,29 +438,113 @@ def bench_serve(args, torch, np):
     serving.run_open_loop(srv, graphs[:64], np.zeros(64), mapped=True)
     srv.close()
     serving.run_plain(graphs[:64], np.zeros(64))
+
     def settled():
         # the host loops of both paths run in Python: collect once and freeze
         # what exists, so that no full collection lands inside a timed run
         gc.collect()
         gc.freeze()
 
+    results = {}
     for mode, arr in (("open_loop", tr.arrivals), ("saturation", np.zeros_like(tr.arrivals))):
-        srv = server()
-        settled()
-        lat, span, _ = serving.run_open_loop(srv, graphs, arr, mapped=True)
-        s = srv.stats()
-        srv.close()
-        p50, p99 = pct(lat)
-        settled()
-        lat_p, span_p, _ = serving.run_plain(graphs, arr)
-        q50, q99 = pct(lat_p)
-        out[mode] = {"server": {"graphs_per_s": len(graphs) / span, "p50_ms": p50, "p99_ms": p99,
-                                "steps": int(s.steps)},
-                     "plain": {"graphs_per_s": len(graphs) / span_p, "p50_ms": q50, "p99_ms": q99},
-                     "throughput_ratio": span_p / span}
-        log(f"serving {mode}: server {len(graphs) / span:.0f} graphs/s p99 {p99:.2f} ms; "
-            f"plain {len(graphs) / span_p:.0f} graphs/s p99 {q99:.2f} ms")
+        got = {}
+        for path in ("server", "plain"):
+            done = [None] * len(graphs)
+
+            def keep(i, lab, its, done=done):
+                done[i] = (lab, its)  # kept by reference; compared after the run
+            settled()
+            if path == "server":
+                srv = server()
+                lat, span, _ = serving.run_open_loop(srv, graphs, arr, on_done=keep, mapped=True)
+                steps = int(srv.stats().steps)
+                srv.close()
+            else:
+                lat, span, _ = serving.run_plain(graphs, arr, on_done=keep)
+            gc.unfreeze()
+            if mode == "open_loop":
+                # steady state: requests arriving after the warm-up, over the
+                # time from the first of them to the last completion
+                sel = measured
+                t_first = float(tr.arrivals[measured].min())
+                rate = nmeas / (span - t_first)
+            else:
+                sel = np.ones(len(graphs), dtype=bool)
+                rate = len(graphs) / span
+            p50, p99 = pct(lat[sel])
+            got[path] = {"graphs_per_s": rate, "p50_ms": p50, "p99_ms": p99}
+            if path == "server":
+                got[path]["steps"] = steps
+            results[(mode, path)] = done
+        got["throughput_ratio"] = got["server"]["graphs_per_s"] / got["plain"]["graphs_per_s"]
+        out[mode] = got
+        log(f"serving {mode}: server {got['server']['graphs_per_s']:.0f} graphs/s p50 {got['server']['p50_ms']:.2f}"
+            f" p99 {got['server']['p99_ms']:.2f} ms; plain {got['plain']['graphs_per_s']:.0f} graphs/s p50 "
+            f"{got['plain']['p50_ms']:.2f} p99 {got['plain']['p99_ms']:.2f} ms")
+    if want_check:
+        out.update(serve_oracle(np, graphs, tr.arrivals, measured, results))
     return out
+
+
+def serve_oracle(np, graphs, arrivals, measured, results):
+    """CPU-baseline leg of serving: union-find and Algorithm 2 once per
+    distinct request graph (the trace draws from pools), union-find's solve
+    time per request as a latency distribution, and every served request's
+    labels and iteration count (server and plain, open loop and saturation)
+    against them."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    uniq = {}
+    for g in graphs:
+        uniq.setdefault(id(g), g)
+    pool = list(uniq.values())
+    uf_t = {}
+    for g in pool:  # one core, one graph at a time: the per-request solve time
+        t = time.perf_counter()
+        oracle.uf_labels(g.n, g.row_ptr, g.col)
+        uf_t[id(g)] = time.perf_counter() - t
+    with ThreadPoolExecutor(oracle_workers()) as ex:
+        ufl = dict(zip([id(g) for g in pool], ex.map(lambda g: oracle.uf_labels(g.n, g.row_ptr, g.col), pool)))
+        its = dict(zip([id(g) for g in pool], ex.map(lambda g: oracle.fastsv_alg2(g.n, g.row_ptr, g.col).iterations,
+                                                      pool)))
+    bad = {}
+    for key, done in results.items():
+        nbad = 0
+        for i, g in enumerate(graphs):
+            lab, it = done[i]
+            if it != its[id(g)] or not np.array_equal(lab, ufl[id(g)]):
+                nbad += 1
+        bad["/".join(key)] = nbad
+    lat = np.array([uf_t[id(g)] for g, m in zip(graphs, measured) if m])
+    return {"labels_match_oracle": all(v == 0 for v in bad.values()),
+            "mismatched_requests": bad,
+            "cpu_oracle": {"union_find_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                           "union_find_p99_ms": float(np.percentile(lat, 99) * 1e3), "cores": 1,
+                           "sample": f"union-find solve time of each measured request's graph "
+                                     f"({len(pool)} distinct graphs), one core"}}
+
+
+def cpu_oracle_table(np, c2, c2_iters):
+    """Oracle timings on C1..C3, one core: union-find (edges/s) and Algorithm 2
+    (time and iteration count; the GPU's count is given beside it)."""
+    import oracle
+    from paper_1910_05971_amd import graphgen as gg
+    rows = {}
+    for name, g in (("er_n65536_m262144", gg.c1_er()), ("rmat_scale24_ef16", c2),
+                    ("grid_4096x4096_p0.55", gg.c3_grid())):
+        t = time.perf_counter()
+        oracle.uf_labels(g.n, g.row_ptr, g.col)
+        t_uf = time.perf_counter() - t
+        t = time.perf_counter()
+        r = oracle.fastsv_alg2(g.n, g.row_ptr, g.col)
+        t_a2 = time.perf_counter() - t
+        rows[name] = {"union_find_ms": 1e3 * t_uf, "union_find_edges_per_s": g.m_eff / t_uf,
+                      "alg2_ms": 1e3 * t_a2, "alg2_edges_per_s": g.m_eff / t_a2, "alg2_iterations": r.iterations}
+        if name == "rmat_scale24_ef16":
+            rows[name]["gpu_iterations"] = c2_iters
+        log(f"cpu oracle {name}: union-find {1e3 * t_uf:.0f} ms, Algorithm 2 {1e3 * t_a2:.0f} ms "
+            f"({r.iterations} iterations)")
+    return rows
 
 
 def main():
@@ -432,10 +585,19 @@ def main():
         out["cpu_baseline"] = res["cpu_baseline"]
     if not args.no_extras and args.workload == "rmat24":
         out["extras"] = bench_extras(fs, torch, np, res["graph"], res["labels"])
+    batch_gpu = None
     if not args.no_batch:
-        out["batched"] = bench_batch(fs, torch, np)
+        out["batched"], batch_gpu = bench_batch(fs, torch, np)
     if not args.no_serve:
-        out["serving"] = bench_serve(args, torch, np)
+        out["serving"] = bench_serve(args, torch, np, want_check=not args.no_cpu_baseline)
+    if not args.no_cpu_baseline:
+        # the rest of the oracle's baseline (outside every timed GPU region)
+        out["cpu_host"] = host_info()
+        if batch_gpu is not None:
+            log("cpu oracle over the batch (one core and all cores)")
+            out["batched"].update(batch_oracle(np, *batch_gpu))
+        if args.workload == "rmat24":
+            out["cpu_oracle_table"] = cpu_oracle_table(np, res["graph"], out["config"]["iterations"])
     print(json.dumps(out), flush=True)
 
 

@@ -77,3 +77,19 @@ def test_defaults_and_sizes():
     lib = binding.load_library()
     assert lib.fastsv_strerror(0) == b"ok"
     assert b"max_iters" in lib.fastsv_strerror(-6)
+
+
+def test_null_context_is_refused_before_any_device_call():
+    """A null context is the first argument check of every compute entry point:
+    FASTSV_EINVAL, returned before any HIP call (so this runs without a GPU)."""
+    import ctypes
+    from paper_1910_05971_amd import binding as b
+    lib = b.load_library()
+    null = ctypes.c_void_p(0)
+    opts, stats = b.default_opts(), b.Stats()
+    o, s = ctypes.byref(opts), ctypes.byref(stats)
+    assert lib.fastsv_cc_csr(null, 4, 6, null, null, null, null, 0, null, o, s) == b.FASTSV_EINVAL
+    assert lib.fastsv_cc_csr_warm(null, 4, 6, null, null, null, null, null, 0, null, o, s) == b.FASTSV_EINVAL
+    assert lib.fastsv_cc_edges(null, 4, 3, null, null, null, null, 0, null, o, s) == b.FASTSV_EINVAL
+    assert lib.fastsv_cc_batch_csr(null, 1, 4, 6, null, null, null, null, null, null, null, 0, null, o,
+                                   s) == b.FASTSV_EINVAL

@@ -144,3 +144,35 @@ def test_server_batch_submit(gpu_ok, mapped):
     for i, g in enumerate(gs):
         assert np.array_equal(got[i][0], want[i][0]), g.name
         assert got[i][1] == want[i][1], (g.name, got[i][1], want[i][1])
+
+
+@pytest.mark.slow
+def test_server_request_trace_with_rmat20(gpu_ok):
+    """The serving workload's own mix, shortened: Poisson arrivals of Erdos-
+    Renyi graphs from the batch distribution and R-MAT scale-20 edge-factor-16
+    graphs (5% here instead of 1%, so that several overlap), page-locked, with
+    the benchmark's pool sizes, replayed open loop; every request against its
+    oracle labels and Algorithm 2 iteration count."""
+    import sys
+    from paper_1910_05971_amd import serving
+    tr = gg.request_trace(400, 2000.0, seed=55, er_pool=48, rmat_pool=2, rmat_frac=0.05)
+    assert tr.kinds.sum() >= 5
+    graphs = serving.pin_graphs(tr.graphs)
+    want = {}
+    for g in graphs:
+        if id(g) not in want:
+            want[id(g)] = _expected(g)
+    print(f"[gpu] serving trace: {len(graphs)} requests, {int(tr.kinds.sum())} R-MAT scale 20", flush=True)
+    sys.stdout.flush()
+    got = [None] * len(graphs)
+
+    def keep(i, lab, its):
+        got[i] = (lab.copy(), its)
+    srv = serving.Server(max_vertices=16_000_000, max_entries=320_000_000, max_slots=2048, validate=False)
+    serving.run_open_loop(srv, graphs, tr.arrivals, on_done=keep, mapped=True)
+    srv.close()
+    for i, g in enumerate(graphs):
+        lab, its = want[id(g)]
+        assert got[i] is not None, i
+        assert np.array_equal(got[i][0], lab), (i, g.name)
+        assert got[i][1] == its, (i, g.name, got[i][1], its)

@@ -30,16 +30,25 @@ def _graphs():
     n = 300
     path = P.csr_from_pairs(n, [(i, i + 1) for i in range(n - 1)])
     star = P.csr_from_pairs(64, [(63, i) for i in range(63)])
+    a = P.csr_from_pairs(6, [(0, 2), (2, 3), (3, 4), (4, 5), (5, 1)])
+    b = P.csr_from_pairs(6, [(0, 1), (1, 2), (2, 4), (4, 3), (3, 5)])
     return [gg.Graph("path300", n, *path, n - 1), gg.Graph("star_last64", 64, *star, 63),
-            gg.rmat(11, 8, seed=71), gg.er(4000, 6000, seed=72), gg.grid(40, 50, 0.55, seed=73)]
+            gg.Graph("path6_hook_condition", 6, *a, 5), gg.Graph("path6_grandparent", 6, *b, 5),
+            gg.rmat(11, 8, seed=71), gg.rmat(13, 16, seed=74), gg.er(4000, 6000, seed=72),
+            gg.grid(40, 50, 0.55, seed=73)]
 
 
-def _solve(rp, col, **kw):
+def _solve(rp, col, expect_capped=None, **kw):
+    """expect_capped: True asserts FASTSV_ENOTCONVERGED exactly, False
+    FASTSV_OK; None accepts either for a capped run."""
     import paper_1910_05971_amd as fs
     labels, stats, st = fs.cc_csr(rp, col, check=False, **kw)
     torch.cuda.synchronize()
-    ok = (fs.FASTSV_OK, fs.FASTSV_ENOTCONVERGED) if kw.get("max_iters") else (fs.FASTSV_OK,)
-    assert st in ok, f"status {st}"
+    if expect_capped is None:
+        ok = (fs.FASTSV_OK, fs.FASTSV_ENOTCONVERGED) if kw.get("max_iters") else (fs.FASTSV_OK,)
+    else:
+        ok = (fs.FASTSV_ENOTCONVERGED,) if expect_capped else (fs.FASTSV_OK,)
+    assert st in ok, f"status {st}, expected one of {ok}"
     return labels.cpu().numpy(), stats
 
 
@@ -51,13 +60,13 @@ def test_variant_trajectories(gpu_ok, flags):
         col = torch.from_numpy(np.ascontiguousarray(g.col)).cuda()
         ref = O.sv_variant(g.n, g.row_ptr, g.col, flags, max_iters=CAP, trace_cap=CAP)
         assert ref.iterations > 0, (g.name, flags, ref.iterations)
-        got, st = _solve(rp, col, sv_flags=flags, max_iters=CAP)
+        got, st = _solve(rp, col, sv_flags=flags, max_iters=CAP, expect_capped=False)
         assert np.array_equal(got, ref.f), (g.name, flags)
         assert st.iterations == ref.iterations, (g.name, flags, st.iterations, ref.iterations)
         k = min(ref.iterations, 64)
         assert st.changed_list()[:k] == ref.changed[:k].tolist(), (g.name, flags)
         for it in range(1, min(ref.iterations, 12) + 1):
-            got_k, _ = _solve(rp, col, sv_flags=flags, max_iters=it)
+            got_k, _ = _solve(rp, col, sv_flags=flags, max_iters=it, expect_capped=it < ref.iterations)
             assert np.array_equal(got_k, ref.trace[it - 1]), (g.name, flags, it)
 
 
