@@ -49,7 +49,9 @@ typedef enum {
     FASTSV_ENOMEM = -4,        /* device or pinned host allocation failed */
     FASTSV_EHIP = -5,          /* a HIP runtime call failed */
     FASTSV_ENOTCONVERGED = -6, /* max_iters iterations ran without meeting the termination test */
-    FASTSV_EBUSY = -7          /* resource in use (serving: no free slot) */
+    FASTSV_EBUSY = -7,         /* resource in use (serving: no free slot) */
+    FASTSV_ESCRATCH = -8       /* the call needs more workspace than the library's fixed scratch
+                                  memory holds (fastsv_cc_csr_noalloc) */
 } fastsv_status;
 
 typedef struct fastsv_ctx fastsv_ctx;
@@ -206,6 +208,31 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_
 int fastsv_cc_csr_warm(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_ptr, const int32_t *d_col_idx,
                        const int32_t *d_f_init, int32_t *d_labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
                        const fastsv_opts *opts, fastsv_stats *stats);
+
+/*
+ * fastsv_cc_csr for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid it).
+ * The call allocates nothing: its workspace is a fixed array of
+ * FASTSV_NOALLOC_SCRATCH_BYTES bytes that the library holds in device
+ * memory, one per GPU, for as long as the process runs (its address on a
+ * device is resolved once, when the first context on that device is
+ * created).  Arguments, options, statistics and results are those of
+ * fastsv_cc_csr with d_ws = NULL, and the same kernels run.
+ *   FASTSV_ESCRATCH  fastsv_workspace_bytes_opts(n, nnz, opts) exceeds
+ *                    FASTSV_NOALLOC_SCRATCH_BYTES (about 3 million vertices
+ *                    with the plain passes; graphs that take the binned
+ *                    layout need about 4 more bytes per stored entry); the
+ *                    labels are then untouched.
+ * Every call on a device uses that device's one array, and a call leaves its
+ * contents behind (each call initialises what it reads).  Calls that overlap
+ * in time on one device (from several host threads or contexts) race on it;
+ * calls made one after another from one thread do not, since a call returns
+ * after its last kernel has finished.
+ */
+#define FASTSV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fastsv_cc_csr_noalloc(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *d_row_ptr,
+                          const int32_t *d_col_idx, int32_t *d_labels, hipStream_t stream,
+                          const fastsv_opts *opts, fastsv_stats *stats);
 
 /*
  * Edge-list entry (the problem statement of Sec. 1 and the edge form of

@@ -29,11 +29,14 @@ FASTSV_ENOMEM = -4
 FASTSV_EHIP = -5
 FASTSV_ENOTCONVERGED = -6
 FASTSV_EBUSY = -7
+FASTSV_ESCRATCH = -8
 
-__all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "cc_edges", "cc_batch_csr", "workspace_bytes",
+NOALLOC_SCRATCH_BYTES = 64 << 20  # FASTSV_NOALLOC_SCRATCH_BYTES
+
+__all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "cc_csr_noalloc", "cc_edges", "cc_batch_csr", "workspace_bytes",
            "load_library", "make_opts", "default_opts", "context", "SV_FLAGS",
            "FASTSV_OK", "FASTSV_EINVAL", "FASTSV_ERANGE", "FASTSV_EOVERFLOW", "FASTSV_ENOMEM",
-           "FASTSV_EHIP", "FASTSV_ENOTCONVERGED", "FASTSV_EBUSY"]
+           "FASTSV_EHIP", "FASTSV_ENOTCONVERGED", "FASTSV_EBUSY", "FASTSV_ESCRATCH", "NOALLOC_SCRATCH_BYTES"]
 
 
 class Opts(ctypes.Structure):
@@ -103,6 +106,9 @@ def load_library():
             lib.fastsv_cc_csr.restype = ctypes.c_int
             lib.fastsv_cc_csr.argtypes = [vp, i32, i64, vp, vp, vp, vp, sz, vp,
                                           ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+            lib.fastsv_cc_csr_noalloc.restype = ctypes.c_int
+            lib.fastsv_cc_csr_noalloc.argtypes = [vp, i32, i64, vp, vp, vp, vp, ctypes.POINTER(Opts),
+                                                  ctypes.POINTER(Stats)]
             lib.fastsv_cc_csr_warm.restype = ctypes.c_int
             lib.fastsv_cc_csr_warm.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, sz, vp,
                                                ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
@@ -252,6 +258,40 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
         return labels, stats, st
     if st != FASTSV_OK:
         raise FastSVError(st, "fastsv_cc_csr_warm" if f_init is not None else "fastsv_cc_csr")
+    return labels, stats
+
+
+def cc_csr_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
+                   stream: torch.cuda.Stream | None = None, max_iters=None, frontier_tau=None, validate=None,
+                   timing=None, blocked=None, block_shift=None, binned=None, bin_shift=None, sv_flags=None,
+                   mode=None, check=True):
+    """cc_csr through fastsv_cc_csr_noalloc: the library allocates no device
+    memory during the call (its workspace is the library's fixed scratch
+    array).  ``labels`` may be preallocated so that the whole call allocates
+    nothing.  Returns (labels, stats), or (labels, stats, status) with
+    ``check=False``."""
+    _check_vec(row_ptr, "row_ptr")
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr needs n+1 >= 1 entries")
+    _check_vec(col, "col")
+    dev = row_ptr.device
+    if col.device != dev:
+        raise ValueError("row_ptr and col must be on the same device")
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+    _check_vec(labels, "labels", n)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift, sv_flags,
+                     mode)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    stats = Stats()
+    lib = load_library()
+    st = lib.fastsv_cc_csr_noalloc(context(_dev_index(dev)), n, col.numel(), _ptr(row_ptr), _ptr(col), _ptr(labels),
+                                   ctypes.c_void_p(s.cuda_stream), ctypes.byref(opts), ctypes.byref(stats))
+    if not check:
+        return labels, stats, st
+    if st != FASTSV_OK:
+        raise FastSVError(st, "fastsv_cc_csr_noalloc")
     return labels, stats
 
 

@@ -36,6 +36,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "fastsv.h"
@@ -431,6 +432,42 @@ struct fastsv_ctx {
 
 int fsv::ctx_device(const fastsv_ctx *ctx) { return ctx->device; }
 
+// Workspace of fastsv_cc_csr_noalloc: a fixed array that every device holding
+// this code object keeps for the life of the process.  In host code its name
+// only stands in for the symbol; the device address of each GPU's copy is
+// taken once per device with hipGetSymbolAddress (with that device current)
+// and used wherever host code passes the array on.
+static __device__ __align__(256) unsigned char scratch[FASTSV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+int resolve_scratch(int device) {
+    if (device < 0 || device >= kScratchDevices) return FASTSV_OK;  // noalloc calls refuse such devices
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return FASTSV_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        if (getenv("FASTSV_DEBUG")) fprintf(stderr, "fastsv: hipGetSymbolAddress(scratch): %s\n", hipGetErrorString(e));
+        return FASTSV_EHIP;
+    }
+    g_scratch_ptr[device] = p;
+    return FASTSV_OK;
+}
+
+void *scratch_ptr(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 namespace {
 
 bool opts_ok(const fastsv_opts &o, int64_t n) {
@@ -495,10 +532,6 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
     const int64_t ntiles = L.ntiles;
     const int fl = opts.sv_flags;
     const bool grand = fl & 1, stoch = fl & 2, early = fl & 8;
-    if (opts.timing && !ctx->events) {
-        for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
-        ctx->events = true;
-    }
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
     launch_init(stream, n, w.F[0], w.F[1], P.G, w.M, 0);
     launch_build_tiles(stream, n, 0, 0, (int)P.nnz, P.rp, w.tiles);
@@ -575,10 +608,6 @@ int solve_async(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Worksp
                 const fastsv_opts &opts, fastsv_stats *stats, int &it) {
     const int n = P.n;
     const int64_t ntiles = L.ntiles;
-    if (opts.timing && !ctx->events) {
-        for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
-        ctx->events = true;
-    }
     int *f = P.G;
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
     if (P.f_init) {
@@ -649,10 +678,6 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
     const int64_t nnz = P.nnz;
     const int64_t ntiles = L.ntiles;
     const bool base = P.vbase != nullptr;
-    if (opts.timing && !ctx->events) {
-        for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
-        ctx->events = true;
-    }
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, stream, w.ctr);
     // iteration 1 reads F from F[0] and writes Fn = F[1]; F = gf = mngf = Fn =
     // iota, or all equal to the given initial parent vector (Alg. 3 duplicates
@@ -916,6 +941,7 @@ const char *fastsv_strerror(int s) {
         case FASTSV_EHIP: return "HIP runtime error";
         case FASTSV_ENOTCONVERGED: return "not converged within max_iters";
         case FASTSV_EBUSY: return "busy";
+        case FASTSV_ESCRATCH: return "workspace exceeds the library's fixed scratch memory";
         default: return "unknown status";
     }
 }
@@ -936,6 +962,19 @@ int fastsv_create(fastsv_ctx **out, int device) {
         return FASTSV_ENOMEM;
     }
     memset(c->host_ctr, 0, sizeof(Counters));
+    // timing events are made here, so that no solve call creates runtime objects
+    for (auto &e : c->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            fastsv_destroy(c);
+            return FASTSV_EHIP;
+        }
+        c->events = true;
+    }
+    const int rs = resolve_scratch(device);
+    if (rs != FASTSV_OK) {
+        fastsv_destroy(c);
+        return rs;
+    }
     *out = c;
     return FASTSV_OK;
 }
@@ -944,7 +983,8 @@ void fastsv_destroy(fastsv_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->events)
-        for (auto &e : c->ev) (void)hipEventDestroy(e);
+        for (auto &e : c->ev)
+            if (e) (void)hipEventDestroy(e);
     if (c->ws) (void)hipFree(c->ws);
     if (c->host_ctr) (void)hipHostFree(c->host_ctr);
     delete c;
@@ -966,9 +1006,11 @@ size_t fastsv_workspace_bytes_opts(int32_t n, int64_t nnz, const fastsv_opts *op
 
 namespace {
 
+// noalloc: the workspace is the device's copy of `scratch` (d_ws and
+// ws_bytes are ignored), and a layout that does not fit it is refused.
 int cc_csr_impl(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col, const int32_t *f_init,
                 int32_t *labels, void *d_ws, size_t ws_bytes, hipStream_t stream, const fastsv_opts *opts_in,
-                fastsv_stats *stats) {
+                fastsv_stats *stats, bool noalloc = false) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!ctx) return FASTSV_EINVAL;
     if (n < 0 || nnz < 0) return FASTSV_EINVAL;
@@ -980,6 +1022,12 @@ int cc_csr_impl(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, cons
     if (!rp || !labels || (nnz > 0 && !col)) return FASTSV_EINVAL;
     if (f_init && opts.sv_flags != kSvFastSV) return FASTSV_EINVAL;  // the variants start from the identity
     const Layout L = layout_for(n, nnz, layout_opts(opts));
+    if (noalloc) {
+        if (L.total > FASTSV_NOALLOC_SCRATCH_BYTES) return FASTSV_ESCRATCH;
+        d_ws = scratch_ptr(ctx->device);
+        if (!d_ws) return FASTSV_EINVAL;  // a device the scratch table does not cover
+        ws_bytes = FASTSV_NOALLOC_SCRATCH_BYTES;
+    }
     HIP_TRY(hipSetDevice(ctx->device));
     int st = get_workspace(ctx, d_ws, ws_bytes, L.total);
     if (st != FASTSV_OK) return st;
@@ -1017,6 +1065,11 @@ int fastsv_cc_csr(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, co
                   int32_t *labels, void *d_ws, size_t ws_bytes, hipStream_t stream,
                   const fastsv_opts *opts, fastsv_stats *stats) {
     return cc_csr_impl(ctx, n, nnz, rp, col, nullptr, labels, d_ws, ws_bytes, stream, opts, stats);
+}
+
+int fastsv_cc_csr_noalloc(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+                          int32_t *labels, hipStream_t stream, const fastsv_opts *opts, fastsv_stats *stats) {
+    return cc_csr_impl(ctx, n, nnz, rp, col, nullptr, labels, nullptr, 0, stream, opts, stats, true);
 }
 
 int fastsv_cc_csr_warm(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,

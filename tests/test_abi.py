@@ -90,6 +90,8 @@ def test_null_context_is_refused_before_any_device_call():
     o, s = ctypes.byref(opts), ctypes.byref(stats)
     assert lib.fastsv_cc_csr(null, 4, 6, null, null, null, null, 0, null, o, s) == b.FASTSV_EINVAL
     assert lib.fastsv_cc_csr_warm(null, 4, 6, null, null, null, null, null, 0, null, o, s) == b.FASTSV_EINVAL
+    assert lib.fastsv_cc_csr_noalloc(null, 4, 6, null, null, null, null, o, s) == b.FASTSV_EINVAL
+    assert b"scratch" in lib.fastsv_strerror(b.FASTSV_ESCRATCH)
     assert lib.fastsv_cc_edges(null, 4, 3, null, null, null, null, 0, null, o, s) == b.FASTSV_EINVAL
     assert lib.fastsv_cc_batch_csr(null, 1, 4, 6, null, null, null, null, null, null, null, 0, null, o,
                                    s) == b.FASTSV_EINVAL
