@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default options instead of the autotuner's choice")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the convergence ablation, asynchronous mode and warm-start measurements")
     ap.add_argument("--serve-requests", type=int, default=22100,
@@ -145,10 +146,28 @@ def bench_solve(args, fs, torch, np):
     rp = torch.from_numpy(g.row_ptr).to(dev)
     col = torch.from_numpy(g.col).to(dev)
     labels = torch.empty(g.n, dtype=torch.int32, device=dev)
-    ws = torch.empty(fs.workspace_bytes(g.n, g.nnz) + 256, dtype=torch.uint8, device=dev)
     kw = {} if args.tau is None else {"frontier_tau": args.tau}
+    # the autotuner picks the threshold, bin width and span for this graph
+    # (none of them changes the iterates); the timed solves use its choice
+    tuning = None
+    if not args.no_tune and args.tau is None:
+        from paper_1910_05971_amd import tune
+        t1 = time.time()
+        rec = tune.tune_csr(rp, col, reps=2, save=False)
+        kw = dict(rec["best"]["opts"])
+        tuning = {"candidates": len(rec["results"]), "best_opts": kw, "best_ms": rec["best"]["ms"],
+                  "default_opts": rec["default"]["opts"], "default_ms": rec["default"]["ms"],
+                  "tuner_s": time.time() - t1}
+        log(f"tuned {kw}: {rec['best']['ms']:.3f} ms vs default {rec['default']['ms']:.3f} ms "
+            f"({len(rec['results'])} candidates, {time.time() - t1:.1f} s)")
+    ws = torch.empty(fs.workspace_bytes(g.n, g.nnz, fs.make_opts(**{k: v for k, v in kw.items()})) + 256,
+                     dtype=torch.uint8, device=dev)
     # validate once, outside the timed region
     fs.cc_csr(rp, col, labels=labels, workspace=ws, validate=True, **kw)
+    # one traced solve, also untimed: the global atomics of every iteration's
+    # hooking (8 B each, a read-modify-write, in the algorithmic bytes)
+    _, tr = fs.cc_csr(rp, col, labels=labels, workspace=ws, trace=True, **kw)
+    atomics = tr.atomics_list()
     for _ in range(args.warmup):
         fs.cc_csr(rp, col, labels=labels, workspace=ws, **kw)
     torch.cuda.synchronize()
@@ -161,10 +180,12 @@ def bench_solve(args, fs, torch, np):
     span = 0
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    per_iter = None
     for _ in range(args.steps):
         _, st = fs.cc_csr(rp, col, labels=labels, workspace=ws, timing=True, **kw)
         iters.append(st.iterations)
-        solve_alg = st.alg_bytes
+        solve_alg = st.alg_bytes + 8 * max(tr.atomics_issued, 0)
+        per_iter = st
         binned = st.binned_iterations > 0
         span = st.bin_span
         fused = st.bin_fused_first == 1
@@ -189,18 +210,25 @@ def bench_solve(args, fs, torch, np):
         except Exception as e:  # a malformed record reads as missing
             traffic_db = {"_error": str(e)}
     kernels = []
+    its = min(per_iter.iterations, 64) if per_iter else 0
+    dense_ks = [k for k in range(1, its) if not per_iter.sparse[k]]
+    # atomics per launch, from the traced solve (its iterates are the timed ones')
+    a_dense = sum(atomics[k] for k in dense_ks) / len(dense_ks) if dense_ks else 0.0
+    a_first = atomics[0] if atomics else 0
     if gather_n:
-        # one dense SpMV step (one launch): row_ptr, col, the G[col] gathers, then G, F, M per row
+        # one dense SpMV step (one launch): row_ptr, col, the G[col] gathers, then G, F, M per row,
+        # and each atomic of the hooks as a read-modify-write
         kernels.append(roofline_record(f"k_bin_pull<{span}>" if binned else "k_tile_reduce<kGather>",
-                                       "one dense SpMV step", 4 * (n + 1) + 8 * nnz + 12 * n,
+                                       "one dense SpMV step", 4 * (n + 1) + 8 * nnz + 12 * n + 8 * a_dense,
                                        gather_ms, gather_n, args.steps, src_hash, traffic_db))
     if fused and first_ms > 0:
         # the layout fill that also performs the first iteration: col and row_ptr
         # read, one 4-byte record per entry written (the markers, at most 256 per
-        # bin, are left out), M and Fn written per row
+        # bin, are left out), M and Fn written per row, the atomics of rows
+        # shared by tiles
         kernels.append(roofline_record("k_bin_fill<true>", "layout fill fused with the first iteration",
-                                       8 * nnz + 12 * n + 4, first_ms, args.steps, args.steps, src_hash,
-                                       traffic_db))
+                                       8 * nnz + 12 * n + 4 + 8 * a_first, first_ms, args.steps, args.steps,
+                                       src_hash, traffic_db))
     # the dominant kernel is the one with the most time per solve
     kernels.sort(key=lambda r: -r["ms_per_solve"])
     # the whole solve: the library's count of algorithmic bytes over all executed
@@ -215,13 +243,23 @@ def bench_solve(args, fs, torch, np):
         "value": g.m_eff * args.steps / elapsed,
         "ms_per_step": 1000.0 * elapsed / args.steps,
         "config": dict(cfg, m_eff=g.m_eff, nnz=g.nnz, iterations=iters[-1] if iters else None,
-                       frontier_tau=args.tau),
+                       frontier_tau=kw.get("frontier_tau"), solver_opts=kw),
+        "tuning": tuning,
         "roofline": kernels[0] if kernels else None,
         "roofline_other": kernels[1:],
         "solve_roofline": solve,
         "breakdown_ms_per_solve": {"first_iteration": first_ms / args.steps, "bin_layout": prep_ms / args.steps,
                                    "dense_steps": gather_ms / args.steps, "sparse_push": sparse_ms / args.steps,
                                    "grandparent": gp_ms / args.steps},
+        # per iteration of the last timed solve: the changed grandparents (the
+        # frontier of the next iteration) as a count and a share of n, the
+        # pass, the edge slots a sparse pass pushed, the hooks' atomics (from
+        # the traced solve) and the kernel times
+        "iterations_detail": [
+            {"k": k + 1, "changed": per_iter.changed[k], "changed_frac": per_iter.changed[k] / n,
+             "pass": "sparse" if per_iter.sparse[k] else ("fill+first" if k == 0 and fused else "dense"),
+             "pushed": per_iter.pushed[k], "atomics": atomics[k] if k < len(atomics) else None,
+             "ms_hook": per_iter.ms_hook[k], "ms_gp": per_iter.ms_gp[k]} for k in range(its)],
     }
     cpu = None
     check = None
@@ -339,7 +377,7 @@ def oracle_workers():
     return max(1, min(16, host_info()["usable_cores"]))
 
 
-def bench_batch(fs, torch, np):
+def bench_batch(fs, torch, np, tuned=True):
     from paper_1910_05971_amd import graphgen as gg
     t0 = time.time()
     b = gg.c4_batch()
@@ -348,11 +386,18 @@ def bench_batch(fs, torch, np):
     vo, eo, rp, col = [torch.from_numpy(np.ascontiguousarray(x)).to(dev)
                        for x in (b.vtx_off, b.edge_off, b.row_ptr, b.col)]
     fs.cc_batch_csr(vo, eo, rp, col, validate=True)
+    bkw, tuning = {}, None
+    if tuned:
+        from paper_1910_05971_amd import tune
+        rec = tune.tune_batch(vo, eo, rp, col, reps=1, save=False)
+        bkw = dict(rec["best"]["opts"])
+        tuning = {"best_opts": bkw, "best_ms": rec["best"]["ms"], "default_ms": rec["default"]["ms"]}
+        log(f"batch tuned {bkw}: {rec['best']['ms']:.2f} ms vs default {rec['default']['ms']:.2f} ms")
     times = []
     for _ in range(3):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        labels, iters, st = fs.cc_batch_csr(vo, eo, rp, col)
+        labels, iters, st = fs.cc_batch_csr(vo, eo, rp, col, **bkw)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
     t_batch = sorted(times)[1]
@@ -377,7 +422,7 @@ def bench_batch(fs, torch, np):
            "graphs": b.num_graphs, "total_edges_undirected": int(b.m_eff.sum()),
            "graphs_per_s": b.num_graphs / t_batch, "ms_per_batch": 1000 * t_batch,
            "iterations": st.iterations, "plain_graphs_per_s": b.num_graphs / t_plain,
-           "speedup_vs_plain": t_plain / t_batch}
+           "speedup_vs_plain": t_plain / t_batch, "tuning": tuning}
     return out, (b, gpu_labels, gpu_iters)
 
 
@@ -429,9 +474,18 @@ def bench_serve(args, torch, np, want_check):
     def pct(lat):
         return float(np.percentile(lat, 50) * 1e3), float(np.percentile(lat, 99) * 1e3)
 
+    pool = (16_000_000, 320_000_000, 2048)  # the trace's working set: about 1.3 GB of CSR and labels state
+    admit = None
+    if not args.no_tune:
+        from paper_1910_05971_amd import tune
+        rec = tune.tune_server(graphs[:2000], pool, save=False)
+        admit = rec["best"]["opts"]["admit_mb"]
+        out["tuning"] = {"best_opts": rec["best"]["opts"], "results": rec["results"],
+                         "sample": "the trace's first 2000 requests submitted at once"}
+        log(f"serving tuned admission: {admit} MB per step")
+
     def server():
-        # pool for the trace's working set: about 1.3 GB of CSR and labels state
-        return serving.Server(max_vertices=16_000_000, max_entries=320_000_000, max_slots=2048, validate=False)
+        return serving.Server(*pool, validate=False, admit_mb=admit)
 
     # warm both paths
     srv = server()
@@ -575,10 +629,12 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": res["config"],
+        "tuning": res["tuning"],
         "roofline": res["roofline"],
         "roofline_other": res["roofline_other"],
         "solve_roofline": res["solve_roofline"],
         "breakdown_ms_per_solve": res["breakdown_ms_per_solve"],
+        "iterations_detail": res["iterations_detail"],
         "labels_match_oracle": res["labels_match_oracle"],
     }
     if res["cpu_baseline"]:
@@ -587,7 +643,7 @@ def main():
         out["extras"] = bench_extras(fs, torch, np, res["graph"], res["labels"])
     batch_gpu = None
     if not args.no_batch:
-        out["batched"], batch_gpu = bench_batch(fs, torch, np)
+        out["batched"], batch_gpu = bench_batch(fs, torch, np, tuned=not args.no_tune)
     if not args.no_serve:
         out["serving"] = bench_serve(args, torch, np, want_check=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:

@@ -49,7 +49,8 @@ typedef enum {
     FASTSV_ENOMEM = -4,        /* device or pinned host allocation failed */
     FASTSV_EHIP = -5,          /* a HIP runtime call failed */
     FASTSV_ENOTCONVERGED = -6, /* max_iters iterations ran without meeting the termination test */
-    FASTSV_EBUSY = -7,         /* resource in use (serving: no free slot) */
+    FASTSV_EBUSY = -7,         /* resource in use (serving: a request's admission copies are still
+                                  in flight, see fastsv_server_cancel) */
     FASTSV_ESCRATCH = -8       /* the call needs more workspace than the library's fixed scratch
                                   memory holds (fastsv_cc_csr_noalloc) */
 } fastsv_status;
@@ -74,12 +75,6 @@ typedef struct {
                                every column id on the device before solving (FASTSV_ERANGE) */
     int32_t timing;         /* 1: time every kernel with HIP events on the call's stream
                                (fills fastsv_stats.ms_hook / ms_gp) */
-    int32_t blocked;        /* column-blocked dense SpMV passes (need rows sorted by column id;
-                               otherwise the plain pass runs): 1 use them; 0 or -1 (automatic,
-                               the default, currently equal to 0) do not.  Same iterates either way. */
-    int32_t block_shift;    /* log2 of the column-block width in vertices; 0 = automatic (2^19,
-                               widened so that there are at most 64 blocks).  4..30 otherwise, and
-                               the graph must then have at most 64 blocks. */
     int32_t binned;         /* binned dense SpMV: the stored entries are regrouped once per call
                                by bins of consecutive vertices of their column (a 4-byte record per
                                entry, plus at most ((n-1) >> 16) + 1 per bin for the high bits of
@@ -108,6 +103,21 @@ typedef struct {
                                sv_flags = 15, runs dense pull passes only, and is refused by the
                                batch entry point.  stats.changed counts the values each pass
                                lowered. */
+    int32_t trace;          /* 1: count on the device the global atomics that hooking issues
+                               (fastsv_stats.atomics_issued and atomics[k]); every wave of a hooking
+                               kernel then issues one more atomic of its own, so traced runs are
+                               for measurement, not for timing.  Counted for sv_flags = 15 in
+                               mode 0 (fastsv_cc_csr, _warm, _noalloc, _edges and the batch).
+                               0 (default): not counted, atomics_issued = -1.
+                               There is no option that records the iterates themselves: the
+                               iterate f_k of any k is the result of a call with max_iters = k
+                               (FASTSV_ENOTCONVERGED), and the statistics below record the
+                               per-iteration figures. */
+    int32_t bin_span;       /* records per lane and step of the binned dense pass: 16 or 32; 0 =
+                               automatic (32 for bins of at least 2^18 records, else 16).  Same
+                               iterates either way. */
+    int32_t admit_mb;       /* serving only: megabytes of graph data a server step admits once one
+                               graph is in (1..4096; 0 = 128) */
 } fastsv_opts;
 
 #define FASTSV_TRACE_ITERS 64
@@ -118,8 +128,6 @@ typedef struct {
     int32_t dense_iterations;      /* iterations whose SpMV step was the dense pull */
     int32_t sparse_iterations;     /* iterations that pushed from the changed grandparents */
     int32_t num_tiles;             /* edge tiles of the dense kernel */
-    int32_t blocked_prepared;      /* 1 if the column-blocked layout was built in this call */
-    int32_t blocked_iterations;    /* dense iterations that ran the column-blocked passes */
     int32_t binned_iterations;     /* dense iterations that ran the binned passes */
     int32_t num_bins;              /* bins of the binned layout (0 when it was not built) */
     int32_t bin_fused_first;       /* 1 if the layout's fill pass also performed the first
@@ -130,17 +138,22 @@ typedef struct {
                                       its count and scan before the fill (opts.timing) */
     int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */
     int64_t alg_bytes;             /* algorithmic bytes of all executed iterations (4 B per int32
-                                      read or written, each gather counted) */
+                                      read or written, each gather counted; with opts.trace also
+                                      8 B per atomic, a read-modify-write) */
+    int64_t atomics_issued;        /* global atomics issued by hooking over all iterations
+                                      (opts.trace = 1), else -1 */
     double ms_total;               /* host wall time of the call */
     int64_t changed[FASTSV_TRACE_ITERS];  /* entries of gf changed in iteration k (k < 64) */
     int32_t sparse[FASTSV_TRACE_ITERS];   /* 1 if iteration k used the sparse push */
+    int64_t pushed[FASTSV_TRACE_ITERS];   /* edge slots pushed in iteration k (sparse iterations; 0 if dense) */
+    int64_t atomics[FASTSV_TRACE_ITERS];  /* global atomics of iteration k's hooking (opts.trace), else -1 */
     float ms_hook[FASTSV_TRACE_ITERS];    /* hooking kernel time of iteration k (opts.timing) */
     float ms_gp[FASTSV_TRACE_ITERS];      /* grandparent/termination kernel time, with the frontier list
                                              build when one follows (opts.timing) */
 } fastsv_stats;
 
 /* Default options: no iteration cap, frontier_tau = 0.05, no validation, no timing,
- * automatic column blocking. */
+ * automatic binned layout, FastSV (sv_flags = 15), mode 0, no atomics count. */
 fastsv_opts fastsv_default_opts(void);
 
 /* Create a context on HIP device `device` (allocates pinned host counters).
@@ -156,12 +169,11 @@ const char *fastsv_strerror(int status);
  * pair, the MIN-accumulated mngf, the frontier list and its edge offsets),
  * the dense kernel's tile table and counters, and for graphs with more than
  * 2^22 vertices the binned layout (about 4 B per stored entry; see
- * fastsv_opts.binned).  With blocked = 1 the column-blocked copy of the matrix
- * is added (about 3 int32 per stored entry).  Returns 0 for invalid sizes.
+ * fastsv_opts.binned).  Returns 0 for invalid sizes.
  */
 size_t fastsv_workspace_bytes(int32_t n, int64_t nnz);
 
-/* Workspace bytes for the given options (blocked = 1 or block_shift change the
+/* Workspace bytes for the given options (binned and bin_shift change the
  * layout); returns 0 for invalid sizes or options. */
 size_t fastsv_workspace_bytes_opts(int32_t n, int64_t nnz, const fastsv_opts *opts);
 
@@ -243,7 +255,6 @@ int fastsv_cc_csr_noalloc(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t
  * iterates and iteration count equal those of the CSR entry on that matrix.
  *   m          0 <= 2m < 2^31
  *   d_ws       at least fastsv_edges_workspace_bytes(n, m) bytes (or NULL)
- *   opts.blocked / block_shift are ignored (the built rows are unsorted).
  */
 size_t fastsv_edges_workspace_bytes(int32_t n, int64_t m);
 int fastsv_cc_edges(fastsv_ctx *ctx, int32_t n, int64_t m, const int32_t *d_src, const int32_t *d_dst,
@@ -284,13 +295,15 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
  * come first served as soon as a slot, n+1 pool vertices and nnz pool
  * entries are free.  Each fastsv_server_step runs one iteration of the method
  * (Algorithm 3, dense or sparse-frontier SpMV as for fastsv_cc_csr) for ALL
- * resident graphs at once; graphs admitted at a step start their first
- * iteration in it, and a graph retires after the first step in which none of
- * its grandparents changed (termination test of Sec. 3.4 for that graph).
- * Graphs never exchange values, so every request gets exactly the labels and
- * the iteration count it would get alone.  On retirement the local labels
- * are copied into h_labels_out and the iteration count into *h_iters_out, and
- * the ticket becomes available from fastsv_server_poll.
+ * resident graphs at once.  An admitted graph starts its first iteration in
+ * the step that admits it when its copy is small and no request waits behind
+ * it, otherwise in the first step after its copy has completed (a long copy
+ * never holds up the resident graphs).  A graph leaves in the first step in
+ * which none of its grandparents changed (termination test of Sec. 3.4 for
+ * that graph): when that step returns, its local labels are in h_labels_out,
+ * its iteration count in *h_iters_out, and its ticket is available from
+ * fastsv_server_poll.  Graphs never exchange values, so every request gets
+ * exactly the labels and the iteration count it would get alone.
  *
  * Threading: a server is driven from one host thread; it uses `stream` for
  * all device work and synchronises it inside fastsv_server_step.
@@ -298,7 +311,7 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
 typedef struct fastsv_server fastsv_server;
 
 typedef struct {
-    int64_t submitted, admitted, completed, steps, dense_steps, sparse_steps;
+    int64_t submitted, admitted, completed, steps, dense_steps, sparse_steps, cancelled;
 } fastsv_server_stats;
 
 /* Device bytes the pool of a server with these limits occupies. */
@@ -344,12 +357,20 @@ int fastsv_server_submit_batch(fastsv_server *srv, int32_t count, const int32_t 
                                int32_t *const *h_labels_out, int32_t *h_iters_out, uint64_t *tickets,
                                int32_t mapped, int32_t *n_accepted);
 
-/* Admit what fits (at most about 128 MB of graph data per step once one graph
- * is in, so that admission copies overlap the iterations), run one iteration
- * for all resident graphs, retire the converged ones.  Graphs admitted while
- * others are resident start iterating at the next step.  Reports how many
- * graphs are resident and queued after it. */
+/* Admit what fits (at most opts.admit_mb megabytes of graph data per step
+ * once one graph is in, so that admission copies overlap the iterations), run one iteration
+ * for all running graphs, and deliver the ones that converged in it.  Reports
+ * how many graphs are resident (admitted and not yet delivered, including
+ * those whose copies are still in flight) and queued after it. */
 int fastsv_server_step(fastsv_server *srv, int32_t *n_resident, int32_t *n_queued);
+
+/* Cancel a request: a queued one is dropped at once; an admitted one leaves
+ * at the next step, which frees its slot and pool ranges.  Its labels and
+ * iteration count are not written and its ticket is never reported.
+ * FASTSV_EBUSY: the request was admitted but its copies to the device are
+ * still in flight; call again after a step.  FASTSV_EINVAL: no such request
+ * (unknown, or already delivered). */
+int fastsv_server_cancel(fastsv_server *srv, uint64_t ticket);
 
 /* Up to cap tickets completed since the last poll, oldest first. */
 int fastsv_server_poll(fastsv_server *srv, uint64_t *done, int32_t cap, int32_t *n_done);

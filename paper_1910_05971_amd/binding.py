@@ -42,20 +42,20 @@ __all__ = ["FastSVError", "Opts", "Stats", "cc_csr", "cc_csr_noalloc", "cc_edges
 class Opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("frontier_tau", ctypes.c_float),
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("blocked", ctypes.c_int32), ("block_shift", ctypes.c_int32),
                 ("binned", ctypes.c_int32), ("bin_shift", ctypes.c_int32), ("sv_flags", ctypes.c_int32),
-                ("mode", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("trace", ctypes.c_int32), ("bin_span", ctypes.c_int32),
+                ("admit_mb", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("dense_iterations", ctypes.c_int32),
                 ("sparse_iterations", ctypes.c_int32), ("num_tiles", ctypes.c_int32),
-                ("blocked_prepared", ctypes.c_int32), ("blocked_iterations", ctypes.c_int32),
                 ("binned_iterations", ctypes.c_int32), ("num_bins", ctypes.c_int32),
                 ("bin_fused_first", ctypes.c_int32), ("bin_span", ctypes.c_int32), ("ms_bin_prepare", ctypes.c_float),
                 ("frontier_edges", ctypes.c_int64), ("alg_bytes", ctypes.c_int64),
-                ("ms_total", ctypes.c_double),
+                ("atomics_issued", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("changed", ctypes.c_int64 * TRACE_ITERS), ("sparse", ctypes.c_int32 * TRACE_ITERS),
+                ("pushed", ctypes.c_int64 * TRACE_ITERS), ("atomics", ctypes.c_int64 * TRACE_ITERS),
                 ("ms_hook", ctypes.c_float * TRACE_ITERS), ("ms_gp", ctypes.c_float * TRACE_ITERS)]
 
     def changed_list(self):
@@ -63,6 +63,12 @@ class Stats(ctypes.Structure):
 
     def sparse_list(self):
         return [int(self.sparse[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+    def pushed_list(self):
+        return [int(self.pushed[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+    def atomics_list(self):
+        return [int(self.atomics[i]) for i in range(min(self.iterations, TRACE_ITERS))]
 
     def ms_hook_list(self):
         return [float(self.ms_hook[i]) for i in range(min(self.iterations, TRACE_ITERS))]
@@ -154,20 +160,16 @@ def default_opts() -> Opts:
 SV_FLAGS = {"sv1": 0, "sv2": 1, "sv3": 3, "sv4": 7, "sv5": 15}
 
 
-def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None,
-              block_shift=None, binned=None, bin_shift=None, sv_flags=None, mode=None) -> Opts:
-    """blocked, binned: None/"auto" -> automatic, False -> never, True -> always.
+def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, binned=None, bin_shift=None,
+              sv_flags=None, mode=None, trace=None, bin_span=None) -> Opts:
+    """binned: None/"auto" -> automatic, False -> never, True -> always.
     sv_flags: 0..15 or one of SV_FLAGS' names (None: FastSV).
-    mode: None/"jacobi"/0 or "async"/1."""
+    mode: None/"jacobi"/0 or "async"/1.  trace: count the hooks' atomics."""
     o = default_opts()
     if mode is not None:
         o.mode = {"jacobi": 0, "async": 1}[mode] if isinstance(mode, str) else int(mode)
     if sv_flags is not None:
         o.sv_flags = SV_FLAGS[sv_flags] if isinstance(sv_flags, str) else int(sv_flags)
-    if blocked is not None and blocked != "auto":
-        o.blocked = 1 if blocked else 0
-    if block_shift is not None:
-        o.block_shift = int(block_shift)
     if binned is not None and binned != "auto":
         o.binned = 1 if binned else 0
     if bin_shift is not None:
@@ -180,6 +182,10 @@ def make_opts(max_iters=None, frontier_tau=None, validate=None, timing=None, blo
         o.validate = int(bool(validate))
     if timing is not None:
         o.timing = int(bool(timing))
+    if trace is not None:
+        o.trace = int(bool(trace))
+    if bin_span is not None:
+        o.bin_span = int(bin_span)
     return o
 
 
@@ -208,13 +214,15 @@ def _check_vec(t, name, n=None):
 
 def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
            workspace: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
-           max_iters=None, frontier_tau=None, validate=None, timing=None, blocked=None, block_shift=None,
-           binned=None, bin_shift=None, sv_flags=None, mode=None, f_init=None, check=True):
+           max_iters=None, frontier_tau=None, validate=None, timing=None, binned=None, bin_shift=None,
+           sv_flags=None, mode=None, trace=None, bin_span=None, f_init=None, tuned=False, check=True):
     """Connected components of a symmetric int32 CSR graph resident on the GPU.
 
     Returns (labels, stats); labels[u] is the smallest vertex of u's component.
     ``f_init`` (int32[n] on the device, may be ``labels`` itself) starts the
     iteration from that parent vector (fastsv_cc_csr_warm).
+    ``tuned=True`` takes the options the autotuner stored for this device and
+    graph size (``tune.py``), where the call gives none.
     With ``check=False`` the status is returned instead of raising:
     (labels, stats, status)."""
     _check_vec(row_ptr, "row_ptr")
@@ -229,8 +237,15 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift, sv_flags,
-                     mode)
+    if tuned:
+        # options the autotuner picked for this device and graph size (explicit
+        # arguments take precedence); none when nothing was tuned
+        from . import tune
+        t = tune.lookup(dev.index if dev.index is not None else torch.cuda.current_device(), n, nnz)
+        frontier_tau = t.get("frontier_tau", frontier_tau) if frontier_tau is None else frontier_tau
+        bin_shift = t.get("bin_shift", bin_shift) if bin_shift is None else bin_shift
+        bin_span = t.get("bin_span", bin_span) if bin_span is None else bin_span
+    opts = make_opts(max_iters, frontier_tau, validate, timing, binned, bin_shift, sv_flags, mode, trace, bin_span)
     if workspace is None:
         wsb = workspace_bytes(n, nnz, opts)
         if wsb == 0:
@@ -263,8 +278,7 @@ def cc_csr(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | N
 
 def cc_csr_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Tensor | None = None,
                    stream: torch.cuda.Stream | None = None, max_iters=None, frontier_tau=None, validate=None,
-                   timing=None, blocked=None, block_shift=None, binned=None, bin_shift=None, sv_flags=None,
-                   mode=None, check=True):
+                   timing=None, binned=None, bin_shift=None, sv_flags=None, mode=None, trace=None, check=True):
     """cc_csr through fastsv_cc_csr_noalloc: the library allocates no device
     memory during the call (its workspace is the library's fixed scratch
     array).  ``labels`` may be preallocated so that the whole call allocates
@@ -281,8 +295,7 @@ def cc_csr_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, *, labels: torch.Te
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing, blocked, block_shift, binned, bin_shift, sv_flags,
-                     mode)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, binned, bin_shift, sv_flags, mode, trace)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     stats = Stats()
     lib = load_library()
@@ -310,7 +323,8 @@ def _dev_index(dev):
 
 
 def cc_edges(n: int, src: torch.Tensor, dst: torch.Tensor, *, labels=None, workspace=None, stream=None,
-             max_iters=None, frontier_tau=None, validate=None, timing=None, sv_flags=None, mode=None, check=True):
+             max_iters=None, frontier_tau=None, validate=None, timing=None, sv_flags=None, mode=None, trace=None,
+             check=True):
     """Connected components from an undirected edge list (each edge once, any
     orientation).  Returns (labels, stats)."""
     _check_vec(src, "src")
@@ -320,7 +334,7 @@ def cc_edges(n: int, src: torch.Tensor, dst: torch.Tensor, *, labels=None, works
     if labels is None:
         labels = torch.empty(n, dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing, sv_flags=sv_flags, mode=mode)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, sv_flags=sv_flags, mode=mode, trace=trace)
     lib = load_library()
     workspace, ws, wsb = _workspace(int(lib.fastsv_edges_workspace_bytes(int(n), int(m))), dev, workspace)
     s = stream if stream is not None else torch.cuda.current_stream(dev)
@@ -336,7 +350,7 @@ def cc_edges(n: int, src: torch.Tensor, dst: torch.Tensor, *, labels=None, works
 
 def cc_batch_csr(vtx_off: torch.Tensor, edge_off: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, *,
                  labels=None, iters=None, workspace=None, stream=None, max_iters=None, frontier_tau=None,
-                 validate=None, timing=None, check=True):
+                 validate=None, timing=None, trace=None, check=True):
     """Many graphs in one call.  row_ptr is global over the concatenation,
     column ids are local to each graph.  Returns (labels in local ids,
     per-graph iteration counts, stats)."""
@@ -353,7 +367,7 @@ def cc_batch_csr(vtx_off: torch.Tensor, edge_off: torch.Tensor, row_ptr: torch.T
     if iters is None:
         iters = torch.empty(max(g, 1), dtype=torch.int32, device=dev)
     _check_vec(labels, "labels", total_n)
-    opts = make_opts(max_iters, frontier_tau, validate, timing)
+    opts = make_opts(max_iters, frontier_tau, validate, timing, trace=trace)
     lib = load_library()
     workspace, ws, wsb = _workspace(int(lib.fastsv_batch_workspace_bytes(int(total_n), int(total_nnz))), dev,
                                     workspace)

@@ -121,7 +121,8 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                                                           BinDiv bd, int nbins, int nchunks, int chunk_tiles,
                                                           const int *__restrict__ off, int cap,
                                                           unsigned *__restrict__ brec, int *__restrict__ bck,
-                                                          int *__restrict__ M, int *__restrict__ Fn) {
+                                                          int *__restrict__ M, int *__restrict__ Fn,
+                                                          unsigned long long *__restrict__ atom) {
     constexpr int kWaves = kFillThreads / kWave;
     constexpr int kCkMask = (1 << kBinCkShift) - 1;
     static_assert(2 * kRowWin <= kTileEntries, "row windows, row minima and the regrouped loads share the staging arrays");
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
     const int per = (nbins + kFillThreads - 1) / kFillThreads;
     const int b0 = tid * per, b1 = min(b0 + per, nbins);
     for (int b = b0; b < b1; ++b) hist[b] = 0;
+    int na = 0;  // atomics of the first iteration's hooks
     // markers are in place for every value up to hi_done (the same in every thread)
     int hi_done = ch.prev;
     // markers of (hi_done, h] at the cursors of this thread's bins
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                 if (j < cnt) {
                     if (r[j] != rowc) {
                         if (in_lds) atomicMin(&rminw[rowc - T.r_lo], cur_min);
-                        else finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
+                        else na += finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
                         rowc = r[j];
                         cur_min = INT_MAX;
                     }
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                 }
             }
             if (in_lds) atomicMin(&rminw[rowc - T.r_lo], cur_min);
-            else finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
+            else na += finish_row<true>(rowc, cur_min, true, nullptr, Fn, nullptr, M);
         }
         __syncthreads();
         if (kFirst && first_pass && in_lds) {
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
                 const int m = rminw[i];
                 if (m == INT_MAX) continue;
                 const bool shared_row = (i == 0 && wrow[0] < T.e0) || (i == nrows - 1 && wrow[nrows] > T.e1);
-                finish_row<true>(T.r_lo + i, m, shared_row, nullptr, Fn, nullptr, M);
+                na += finish_row<true>(T.r_lo + i, m, shared_row, nullptr, Fn, nullptr, M);
             }
         }
         if (h > hi_done) put_markers(h);
@@ -336,6 +338,7 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
       }
     }
     if (ch.end > hi_done) put_markers(ch.end);
+    if (kFirst) wave_add_atomics(atom, na);
 }
 
 // Dense pass over the binned layout: one workgroup per bin, the bin's W rows
@@ -352,7 +355,8 @@ template <int kPerLaneSpan>
 __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, int cap, const int *__restrict__ off,
                                                    const unsigned *__restrict__ brec, const int *__restrict__ bck,
                                                    const int *__restrict__ F, int *__restrict__ Fn,
-                                                   const int *__restrict__ G, int *__restrict__ M) {
+                                                   const int *__restrict__ G, int *__restrict__ M,
+                                                   unsigned long long *__restrict__ atom) {
     __shared__ int wmin[kBinRowsMax];
     constexpr int kSpan = kWave * kPerLaneSpan;
     static_assert(kSpan % (1 << kBinCkShift) == 0, "every wave starts at a checkpoint");
@@ -414,11 +418,13 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, in
         }
         __syncthreads();
     }
+    int na = 0;
     for (int i = tid; i < rows; i += 1024) {
         const int m = wmin[i];
         if (m == INT_MAX) continue;
-        finish_row<false>(u0 + i, m, false, F, Fn, G, M);
+        na += finish_row<false>(u0 + i, m, false, F, Fn, G, M);
     }
+    wave_add_atomics(atom, na);
 }
 
 }  // namespace fsv

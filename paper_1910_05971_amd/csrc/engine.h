@@ -65,7 +65,9 @@ struct IterCounters {
     // high 32 bits: entries of gf that changed (termination test; they form the
     // frontier list), low 32 bits: their total degree
     unsigned long long packed;
-    unsigned long long pad;
+    // global atomics issued by the iteration's hooking (counted when the
+    // kernels are given this counter)
+    unsigned long long atomics;
 };
 
 struct Counters {
@@ -74,8 +76,6 @@ struct Counters {
     int status;
     int pad[7];
 };
-
-constexpr int kMaxBlocks = 64;
 
 constexpr int kSvFastSV = 15;  // all four changes of Sec. 3: Algorithm 2
 constexpr int kModeJacobi = 0;  // read f, write f_next (Sec. 2.4)
@@ -128,6 +128,14 @@ struct SrvNew {
     int pad;
 };
 
+// A graph resident in the serving pool during one step.
+struct SrvRun {
+    int vb, n;   // pool vertex base, vertices
+    int cancel;  // 1: cancelled, leaves in this step without output
+    int pad;
+};
+constexpr int kSettleChunk = 4096;  // vertices per workgroup of the step's settle pass
+
 // One workgroup's share of the placement of newly admitted graphs.
 struct PlaceChunk {
     int k;      // graph of the step's admission list
@@ -141,17 +149,6 @@ constexpr int kPlaceUnroll = 8;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kScanThreads * kScanItems;
-
-// Per-block description of the column-blocked layout.
-struct CbInfo {
-    int cbb[kMaxBlocks + 1];   // aligned entry base of each block; cbb[nblk] = padded total
-    int len[kMaxBlocks];       // entries of each block
-    int sbb[kMaxBlocks + 1];   // segment base of each block; sbb[nblk] = S
-    int tb[kMaxBlocks + 1];    // phase tile base of each block; tb[nblk] = total phase tiles
-    int flags;                 // bit 0: some row is not sorted
-    int pad[3];
-};
-
 
 inline int grid_for(int64_t items, int per_block, int cap = 1 << 30) {
     int64_t g = (items + per_block - 1) / per_block;
@@ -177,10 +174,12 @@ void launch_init(hipStream_t s, int n, int *F, int *Fn, int *G, int *M, int base
 // tiles of one CSR graph whose entries are [e_begin, e_end) of col and whose
 // rows are [r_begin, r_begin + nrows) with absolute row_ptr values
 void launch_build_tiles(hipStream_t s, int nrows, int r_begin, int e_begin, int e_end, const int *rp, Tile *tiles);
+// atom (nullable): where the hooking kernels add the global atomics they issue
 void launch_dense(hipStream_t s, int mode, const Tile *tiles, int ntiles, const int *rp, const int *col,
-                  const int *vbase, const int *F, int *Fn, const int *G, int *M);
+                  const int *vbase, const int *F, int *Fn, const int *G, int *M, unsigned long long *atom = nullptr);
 void launch_sparse(hipStream_t s, const int *frontier, const int *eoff, int fcnt, int edges, const int *rp,
-                   const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M);
+                   const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M,
+                   unsigned long long *atom = nullptr);
 // the same with the frontier size read on the device from `counts`; frontier
 // vertices v with skip_mark[vbase[v]] == skip_val are not pushed
 void launch_sparse_dev(hipStream_t s, const IterCounters *counts, int max_blocks, const int *frontier,
@@ -201,8 +200,11 @@ void launch_fill(hipStream_t s, int n, int *x, int v);
 void launch_fill_iota(hipStream_t s, int n, int *x);
 
 // serving pool helpers
-void launch_srv_status(hipStream_t s, int nslots, const int *slot_vb, const int *lastk, int step, int *gedge,
-                       int *out_flag, int *out_edges);
+// blocks = blk_off[nrun] (see k_srv_settle); h_flag, h_edges and h_out are
+// device addresses of page-locked host memory
+void launch_srv_settle(hipStream_t s, int nrun, int blocks, const SrvRun *run, const int *blk_off, int step,
+                       int *lastk, int *gedge, int *h_flag, int *h_edges, int *h_out, int *F0, int *F1, int *G,
+                       int *M, int *vbase);
 void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
                             const Tile *pool_tiles, Tile *step_tiles, int *mark, int step);
 void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
@@ -210,7 +212,5 @@ void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, cons
                       int *lastk);
 void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,
                       Tile *tiles);
-void launch_srv_retire(hipStream_t s, int nret, int rows, const SrvNew *desc, const int *row_off, int *out, int *F0,
-                       int *F1, int *G, int *M, int *lastk);
 
 }  // namespace fsv

@@ -30,6 +30,7 @@
 // gives exactly the dense iterate.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cstdint>
@@ -48,34 +49,20 @@ namespace fsv {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int kCbMinShift = 19;  // 2^19 vertices = 2 MB of G per block
-
-inline int cb_shift_for(int64_t n) {
-    int sh = kCbMinShift;
-    while (((n + (int64_t(1) << sh) - 1) >> sh) > kMaxBlocks) ++sh;
-    return sh;
-}
-
 struct Layout {
     int64_t n, nnz, ntiles;
-    bool cb;         // column-blocked arrays present
-    int cb_shift, nblk;
-    int64_t scan_len, scan_sums;
     bool bin;        // binned dense pass arrays present
     BinDiv bdiv;  // bin width W and the divisor for u / W
     int nbins, nchunks, chunk_tiles;
     int64_t bin_scan_len;
     int bin_cap;     // records the binned layout can hold (entries plus markers)
     size_t off_F0, off_F1, off_M, off_frontier, off_eoff, off_fmask, off_tiles, off_ctr;
-    size_t off_cbcol, off_segptr, off_segrow, off_cnte, off_cnts, off_sums_e, off_sums_s, off_cbtiles, off_info;
     size_t off_brec, off_bck, off_bcnt, off_bsums;
     size_t total;
 };
 
 // Dense-pass choices that change the workspace layout.
 struct LayoutOpts {
-    int cb_mode = -1;    // column-blocked: -1 automatic, 0 off, 1 forced
-    int cb_shift = 0;    // 0 = automatic block width
     int bin_mode = -1;   // binned: -1 automatic, 0 off, 1 forced
     int bin_shift = 0;   // 0 = automatic bin width
 };
@@ -83,26 +70,19 @@ struct LayoutOpts {
 // the batch entry point uses the plain passes (column ids are graph-local)
 LayoutOpts batch_layout_opts() {
     LayoutOpts lo;
-    lo.cb_mode = 0;
     lo.bin_mode = 0;
     return lo;
 }
 
 LayoutOpts layout_opts(const fastsv_opts &o) {
     LayoutOpts lo;
-    lo.cb_mode = o.blocked;
-    lo.cb_shift = o.block_shift;
     lo.bin_mode = o.binned;
     lo.bin_shift = o.bin_shift;
-    if (o.sv_flags != kSvFastSV || o.mode == kModeAsync) {  // ablation variants and async: plain passes only
-        lo.cb_mode = 0;
-        lo.bin_mode = 0;
-    }
+    if (o.sv_flags != kSvFastSV || o.mode == kModeAsync) lo.bin_mode = 0;  // ablation variants and async: plain passes only
     return lo;
 }
 
 Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
-    const int cb_mode = lo.cb_mode, shift = lo.cb_shift;
     Layout L{};
     L.n = n;
     L.nnz = nnz;
@@ -118,26 +98,6 @@ Layout layout_for(int64_t n, int64_t nnz, const LayoutOpts &lo = LayoutOpts()) {
     L.off_fmask = take(sizeof(unsigned long long) * (size_t)((n + kWave - 1) / kWave));
     L.off_tiles = take(sizeof(Tile) * (size_t)L.ntiles);
     L.off_ctr = take(sizeof(Counters));
-    // automatic mode does not pick the blocked passes yet: on the measured
-    // workloads their per-segment M traffic and one-time regrouping cost more
-    // than the gathers they keep in L2 (see the design notes); blocked = 1
-    // selects them explicitly
-    L.cb = nnz > 0 && cb_mode == 1;
-    if (L.cb) {
-        L.cb_shift = shift > 0 ? shift : cb_shift_for(n);
-        L.nblk = (int)((n + (int64_t(1) << L.cb_shift) - 1) >> L.cb_shift);
-        L.scan_len = (int64_t)L.nblk * L.ntiles;
-        L.scan_sums = (L.scan_len + kScanBlock - 1) / kScanBlock + 1;
-        L.off_cbcol = take(sizeof(int) * (size_t)(nnz + 4 * kMaxBlocks));
-        L.off_segptr = take(sizeof(int) * (size_t)(nnz + kMaxBlocks + 1));
-        L.off_segrow = take(sizeof(int) * (size_t)nnz);
-        L.off_cnte = take(sizeof(int) * (size_t)L.scan_len);
-        L.off_cnts = take(sizeof(int) * (size_t)L.scan_len);
-        L.off_sums_e = take(sizeof(int) * (size_t)L.scan_sums);
-        L.off_sums_s = take(sizeof(int) * (size_t)L.scan_sums);
-        L.off_cbtiles = take(sizeof(Tile) * (size_t)(L.ntiles + kMaxBlocks));
-        L.off_info = take(sizeof(CbInfo));
-    }
     // binned dense passes: one 32-bit record per stored entry and per marker
     // (see engine.h), the checkpoints of the high source bits, the
     // (bin, chunk) counts and their scan
@@ -190,9 +150,6 @@ struct Workspace {
     unsigned long long *fmask;  // changed vertices of the last grandparent pass, one bit each
     Tile *tiles;
     Counters *ctr;
-    int *cb_col, *seg_ptr, *seg_row, *cnt_e, *cnt_s, *sums_e, *sums_s;
-    Tile *cb_tiles;
-    CbInfo *info;
     unsigned *brec;
     int *bck;
     int *bcnt, *bsums;
@@ -209,17 +166,6 @@ Workspace carve(void *base, const Layout &L) {
     w.fmask = reinterpret_cast<unsigned long long *>(p + L.off_fmask);
     w.tiles = reinterpret_cast<Tile *>(p + L.off_tiles);
     w.ctr = reinterpret_cast<Counters *>(p + L.off_ctr);
-    if (L.cb) {
-        w.cb_col = reinterpret_cast<int *>(p + L.off_cbcol);
-        w.seg_ptr = reinterpret_cast<int *>(p + L.off_segptr);
-        w.seg_row = reinterpret_cast<int *>(p + L.off_segrow);
-        w.cnt_e = reinterpret_cast<int *>(p + L.off_cnte);
-        w.cnt_s = reinterpret_cast<int *>(p + L.off_cnts);
-        w.sums_e = reinterpret_cast<int *>(p + L.off_sums_e);
-        w.sums_s = reinterpret_cast<int *>(p + L.off_sums_s);
-        w.cb_tiles = reinterpret_cast<Tile *>(p + L.off_cbtiles);
-        w.info = reinterpret_cast<CbInfo *>(p + L.off_info);
-    }
     if (L.bin) {
         w.brec = reinterpret_cast<unsigned *>(p + L.off_brec);
         w.bck = reinterpret_cast<int *>(p + L.off_bck);
@@ -238,34 +184,12 @@ void scan_inplace(int *x, int64_t len, int *sums, hipStream_t stream) {
     hipLaunchKernelGGL(k_scan_down, dim3(m), dim3(kScanThreads), 0, stream, x, len, sums, x);
 }
 
-__global__ void k_cb_info_init(CbInfo *info) {
-    if (threadIdx.x == 0) info->flags = 0;
-}
-
-// Build the column-blocked layout (entries, segments, phase tiles).  The
-// caller reads CbInfo back afterwards.
-void cb_prepare(const Layout &L, const Workspace &w, const int *rp, const int *col, hipStream_t stream) {
-    const int nt = (int)L.ntiles;
-    hipLaunchKernelGGL(k_cb_info_init, dim3(1), dim3(64), 0, stream, w.info);
-    hipLaunchKernelGGL(k_cb_count, dim3(nt), dim3(kWave), 0, stream, w.tiles, nt, rp, col, L.cb_shift, L.nblk,
-                       w.cnt_e, w.cnt_s, &w.info->flags);
-    scan_inplace(w.cnt_e, L.scan_len, w.sums_e, stream);
-    scan_inplace(w.cnt_s, L.scan_len, w.sums_s, stream);
-    const int m = grid_for(L.scan_len, kScanBlock);
-    hipLaunchKernelGGL(k_cb_bases, dim3(1), dim3(64), 0, stream, w.cnt_e, w.cnt_s, nt, L.nblk, (int)L.nnz,
-                       w.sums_s + m, w.info);
-    hipLaunchKernelGGL(k_cb_scatter, dim3(nt), dim3(kWave), 0, stream, w.tiles, nt, rp, col, L.cb_shift, L.nblk,
-                       w.cnt_e, w.cnt_s, w.info, w.cb_col, w.seg_ptr, w.seg_row);
-    hipLaunchKernelGGL(k_cb_sentinels, dim3(1), dim3(kMaxBlocks), 0, stream, L.nblk, w.info, w.seg_ptr);
-    hipLaunchKernelGGL(k_cb_tiles, dim3(grid_for(L.nnz, 256)), dim3(256), 0, stream, L.nblk, w.info, w.seg_ptr,
-                       w.cb_tiles);
-}
-
 // Build the binned layout (count, scan, fill).  With M and Fn given, the fill
 // also performs the first iteration's hooking (the grandparent vector is then
 // still the identity).
 void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, const int *col, hipStream_t stream,
-                 int *M = nullptr, int *Fn = nullptr, hipEvent_t before_fill = nullptr) {
+                 int *M = nullptr, int *Fn = nullptr, hipEvent_t before_fill = nullptr,
+                 unsigned long long *atom = nullptr) {
     hipLaunchKernelGGL(k_bin_count, dim3(L.nchunks), dim3(kBinThreads), 0, stream, L.nnz, n, col, w.tiles,
                        (int)L.ntiles, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt);
     scan_inplace(w.bcnt, L.bin_scan_len, w.bsums, stream);
@@ -274,11 +198,11 @@ void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, cons
     if (M)
         hipLaunchKernelGGL(k_bin_fill<true>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
                            n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, L.bin_cap, w.brec, w.bck,
-                           M, Fn);
+                           M, Fn, atom);
     else
         hipLaunchKernelGGL(k_bin_fill<false>, dim3(L.nchunks), dim3(kFillThreads), lds, stream, w.tiles, (int)L.ntiles,
                            n, rp, col, L.bdiv, L.nbins, L.nchunks, L.chunk_tiles, w.bcnt, L.bin_cap, w.brec, w.bck,
-                           nullptr, nullptr);
+                           nullptr, nullptr, nullptr);
 }
 
 // ---- launch wrappers ----
@@ -294,51 +218,55 @@ void launch_build_tiles(hipStream_t s, int nrows, int r_begin, int e_begin, int 
 }
 
 void launch_dense(hipStream_t s, int mode, const Tile *tiles, int ntiles, const int *rp, const int *col,
-                  const int *vbase, const int *F, int *Fn, const int *G, int *M) {
+                  const int *vbase, const int *F, int *Fn, const int *G, int *M, unsigned long long *atom) {
     if (ntiles <= 0) return;
     const dim3 grid(grid_for(ntiles, kHookWaves)), block(kWave * kHookWaves);
     switch (mode) {
         case kDenseIota:
-            hipLaunchKernelGGL((k_tile_reduce<kIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M, 0);
+            hipLaunchKernelGGL((k_tile_reduce<kIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M, 0,
+                               atom);
             break;
         case kDenseGather:
-            hipLaunchKernelGGL((k_tile_reduce<kGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M, 0);
+            hipLaunchKernelGGL((k_tile_reduce<kGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M,
+                               0, atom);
             break;
         case kDenseBaseIota:
             hipLaunchKernelGGL((k_tile_reduce<kBaseIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G,
-                               M, 0);
+                               M, 0, atom);
             break;
         default:
             hipLaunchKernelGGL((k_tile_reduce<kBaseGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn,
-                               G, M, 0);
+                               G, M, 0, atom);
             break;
     }
 }
 
 void launch_sparse(hipStream_t s, const int *frontier, const int *eoff, int fcnt, int edges, const int *rp,
-                   const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M) {
+                   const int *col, const int *vbase, const int *F, int *Fn, const int *G, int *M,
+                   unsigned long long *atom) {
     if (edges <= 0) return;
     const dim3 grid(grid_for(edges, kPushSlots)), block(kPushThreads);
     const IterCounters *none = nullptr;
     const int *no_skip = nullptr;
     if (vbase)
         hipLaunchKernelGGL(k_hook_sparse<true>, grid, block, 0, s, frontier, eoff, fcnt, edges, none, rp, col, vbase,
-                           F, Fn, G, M, no_skip, 0);
+                           F, Fn, G, M, no_skip, 0, atom);
     else
         hipLaunchKernelGGL(k_hook_sparse<false>, grid, block, 0, s, frontier, eoff, fcnt, edges, none, rp, col, vbase,
-                           F, Fn, G, M, no_skip, 0);
+                           F, Fn, G, M, no_skip, 0, atom);
 }
 
 void launch_sparse_dev(hipStream_t s, const IterCounters *counts, int max_blocks, const int *frontier,
                        const int *eoff, const int *rp, const int *col, const int *vbase, const int *F, int *Fn,
                        const int *G, int *M, const int *skip_mark, int skip_val) {
     const dim3 grid(max_blocks > 0 ? max_blocks : 1), block(kPushThreads);
+    unsigned long long *no_count = nullptr;
     if (vbase)
         hipLaunchKernelGGL(k_hook_sparse<true>, grid, block, 0, s, frontier, eoff, 0, 0, counts, rp, col, vbase, F,
-                           Fn, G, M, skip_mark, skip_val);
+                           Fn, G, M, skip_mark, skip_val, no_count);
     else
         hipLaunchKernelGGL(k_hook_sparse<false>, grid, block, 0, s, frontier, eoff, 0, 0, counts, rp, col, vbase, F,
-                           Fn, G, M, skip_mark, skip_val);
+                           Fn, G, M, skip_mark, skip_val, no_count);
 }
 
 void launch_zero_iter(hipStream_t s, IterCounters *ic) {
@@ -371,11 +299,12 @@ void launch_fill(hipStream_t s, int n, int *x, int v) {
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, x, v);
 }
 
-void launch_srv_status(hipStream_t s, int nslots, const int *slot_vb, const int *lastk, int step, int *gedge,
-                       int *out_flag, int *out_edges) {
-    if (nslots <= 0) return;
-    hipLaunchKernelGGL(k_srv_status, dim3(grid_for(nslots, 256)), dim3(256), 0, s, nslots, slot_vb, lastk, step, gedge,
-                       out_flag, out_edges);
+void launch_srv_settle(hipStream_t s, int nrun, int blocks, const SrvRun *run, const int *blk_off, int step,
+                       int *lastk, int *gedge, int *h_flag, int *h_edges, int *h_out, int *F0, int *F1, int *G,
+                       int *M, int *vbase) {
+    if (nrun <= 0 || blocks <= 0) return;
+    hipLaunchKernelGGL(k_srv_settle, dim3(blocks), dim3(256), 0, s, nrun, run, blk_off, step, lastk, gedge, h_flag,
+                       h_edges, h_out, F0, F1, G, M, vbase);
 }
 
 void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
@@ -397,13 +326,6 @@ void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, con
                       Tile *tiles) {
     if (nnew <= 0 || rows <= 0) return;
     hipLaunchKernelGGL(k_srv_tiles, dim3(grid_for(rows, 256, 8192)), dim3(256), 0, s, nnew, desc, row_off, rp, tiles);
-}
-
-void launch_srv_retire(hipStream_t s, int nret, int rows, const SrvNew *desc, const int *row_off, int *out, int *F0,
-                       int *F1, int *G, int *M, int *lastk) {
-    if (nret <= 0 || rows <= 0) return;
-    hipLaunchKernelGGL(k_srv_retire, dim3(grid_for(rows, 256, 8192)), dim3(256), 0, s, nret, desc, row_off, out, F0,
-                       F1, G, M, lastk);
 }
 
 }  // namespace fsv
@@ -472,16 +394,23 @@ namespace {
 
 bool opts_ok(const fastsv_opts &o, int64_t n) {
     if (!(o.frontier_tau >= 0.0f)) return false;  // also rejects NaN
-    if (o.blocked < -1 || o.blocked > 1) return false;
-    if (o.block_shift != 0 && (o.block_shift < 4 || o.block_shift > 30)) return false;
-    if (o.block_shift != 0 && n > 0 && ((n + (int64_t(1) << o.block_shift) - 1) >> o.block_shift) > kMaxBlocks)
-        return false;
     if (o.binned < -1 || o.binned > 1) return false;
     if (o.sv_flags < 0 || o.sv_flags > kSvFastSV) return false;
     if (o.mode != kModeJacobi && o.mode != kModeAsync) return false;
     if (o.mode == kModeAsync && o.sv_flags != kSvFastSV) return false;
     if (o.bin_shift != 0 && (o.bin_shift < kBinShiftMin || o.bin_shift > kBinShiftMax)) return false;
+    if (o.trace != 0 && o.trace != 1) return false;
+    if (o.bin_span != 0 && o.bin_span != kBinSpan && o.bin_span != kBinSpanWide) return false;
+    if (o.admit_mb < 0 || o.admit_mb > 4096) return false;
     return true;
+}
+
+// Statistics before a call: zero, with the atomics marked as not counted.
+void clear_stats(fastsv_stats *stats) {
+    if (!stats) return;
+    memset(stats, 0, sizeof(*stats));
+    stats->atomics_issued = -1;
+    for (auto &a : stats->atomics) a = -1;
 }
 
 // Caller-provided workspace, or the context's own (grown on demand).
@@ -559,7 +488,7 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
                                    (fl & 4) ? 1 : 0);
             else
                 hipLaunchKernelGGL((k_tile_reduce<kVariant>), grid, block, 0, stream, w.tiles, (int)ntiles, P.rp,
-                                   P.col, grand ? G : F, F, Fn, G, w.M, fl);
+                                   P.col, grand ? G : F, F, Fn, G, w.M, fl, (unsigned long long *)nullptr);
         }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
         launch_zero_iter(stream, ic);
@@ -690,7 +619,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         launch_init(stream, n, w.F[0], w.F[1], P.G, w.M, 0);
     launch_build_tiles(stream, n, 0, 0, (int)nnz, P.rp, w.tiles);
     // binned layout: built before the first dense iteration that gathers
-    int bin_state = (L.bin && !base && !L.cb) ? 0 : -1;  // 0 not built, 1 ready, -1 unused
+    int bin_state = (L.bin && !base) ? 0 : -1;  // 0 not built, 1 ready, -1 unused
     // when later iterations will run dense, the layout build also performs the
     // first iteration (it streams the same column ids)
     const bool fuse_first = bin_state == 0 && opts.frontier_tau < 1.0f && !warm;
@@ -703,10 +632,6 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
     bool frontier_ready = false;
     const double tau_edges = (double)opts.frontier_tau * (double)nnz;
     int64_t alg = 0;
-    // column-blocked dense passes: prepared lazily before the first dense
-    // iteration that gathers
-    int cb_state = (L.cb && !base) ? 0 : -1;  // 0 not built, 1 ready, -1 unused
-    CbInfo cbh{};
     for (;;) {
         ++it;
         int *F = w.F[(it + 1) & 1];
@@ -714,20 +639,15 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         fk = Fn;
         IterCounters *ic = &w.ctr->it[it & 1];
         IterCounters *hc = &ctx->host_ctr->it[it & 1];
+        // (the slot was last read by the host after iteration it - 2)
+        launch_zero_iter(stream, ic);
+        unsigned long long *atom = opts.trace ? &ic->atomics : nullptr;
         const bool sparse = it > 1 && frontier_ready && opts.frontier_tau > 0.0f &&
                             (opts.frontier_tau >= 1.0f || (double)prev_edges < tau_edges);
         const int ti = it - 1;
         const bool timed = opts.timing && ti < FASTSV_TRACE_ITERS;
         // iteration 1 gathers too when it starts from a given f
         const bool gathers = it > 1 || warm;
-        if (!sparse && gathers && cb_state == 0) {
-            cb_prepare(L, w, P.rp, P.col, stream);
-            HIP_TRY(hipGetLastError());
-            HIP_TRY(hipMemcpyAsync(&cbh, w.info, sizeof(CbInfo), hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            cb_state = (cbh.flags & 1) ? -1 : 1;  // rows not sorted: keep the plain pass
-            if (stats) stats->blocked_prepared = 1;
-        }
         if (!sparse && gathers && bin_state == 0) {
             if (opts.timing) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
             bin_prepare(L, w, n, P.rp, P.col, stream);
@@ -745,12 +665,12 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
         if (sparse) {
             launch_sparse(stream, w.frontier, w.eoff, (int)prev_fcnt, (int)prev_edges, P.rp, P.col, P.vbase, F, Fn, G,
-                          w.M);
+                          w.M, atom);
             // frontier ids, offsets, row starts and values; per slot col and an M read-modify-write
             alg += 16 * prev_fcnt + 12 * prev_edges;
         } else {
             if (it == 1 && fuse_first) {
-                bin_prepare(L, w, n, P.rp, P.col, stream, w.M, Fn, timed ? ctx->ev[3] : nullptr);
+                bin_prepare(L, w, n, P.rp, P.col, stream, w.M, Fn, timed ? ctx->ev[3] : nullptr, atom);
                 bin_state = 1;
                 if (stats) {
                     stats->num_bins = L.nbins;
@@ -758,41 +678,29 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 }
             } else if (!gathers) {
                 launch_dense(stream, base ? kDenseBaseIota : kDenseIota, w.tiles, (int)ntiles, P.rp, P.col, P.vbase,
-                             F, Fn, G, w.M);
-            } else if (cb_state == 1) {
-                const dim3 hblock(kWave * kHookWaves);
-                for (int b = 0; b < L.nblk; ++b) {
-                    const int nt_b = cbh.tb[b + 1] - cbh.tb[b];
-                    if (nt_b <= 0) continue;
-                    hipLaunchKernelGGL((k_tile_reduce<kPhase>), dim3(grid_for(nt_b, kHookWaves)), hblock, 0, stream,
-                                       w.cb_tiles + cbh.tb[b], nt_b, w.seg_ptr + cbh.sbb[b] + b, w.cb_col,
-                                       w.seg_row + cbh.sbb[b], F, Fn, G, w.M, 0);
-                }
-                hipLaunchKernelGGL(k_hook_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, w.M, G, F, Fn);
-                if (stats) stats->blocked_iterations++;
+                             F, Fn, G, w.M, atom);
             } else if (bin_state == 1) {
                 // wide steps only where bins are long enough that the ragged
                 // last step of each bin is a small share
-                const bool wide = L.bin_cap / L.nbins >= kBinWideMin;
+                const bool wide = opts.bin_span ? opts.bin_span == kBinSpanWide : L.bin_cap / L.nbins >= kBinWideMin;
                 if (wide)
                     hipLaunchKernelGGL(k_bin_pull<kBinSpanWide>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
-                                       L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M);
+                                       L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M, atom);
                 else
                     hipLaunchKernelGGL(k_bin_pull<kBinSpan>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
-                                       L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M);
+                                       L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M, atom);
                 if (stats) {
                     stats->binned_iterations++;
                     stats->bin_span = wide ? kBinSpanWide : kBinSpan;
                 }
             } else {
                 launch_dense(stream, base ? kDenseBaseGather : kDenseGather, w.tiles, (int)ntiles, P.rp, P.col,
-                             P.vbase, F, Fn, G, w.M);
+                             P.vbase, F, Fn, G, w.M, atom);
             }
             // row_ptr, col, gathers of G[col] (none while G is the identity), then G[u], F[u], M[u] per row
             alg += 4 * ((int64_t)n + 1) + (gathers ? 8 : 4) * nnz + 12 * (int64_t)n + (base ? 4 * (int64_t)n : 0);
         }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
-        launch_zero_iter(stream, ic);
         const bool want_frontier = opts.frontier_tau > 0.0f;
         launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 2 : 0, P.lastk, it,
                            P.vbase, nullptr, w.fmask);
@@ -801,9 +709,11 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
+        const int64_t atomics = opts.trace ? (int64_t)hc->atomics : -1;
         // read Fn[u], gather Fn[Fn[u]], read G[u], write G[u] and the next seed
-        // (with the frontier wanted: a mask bit per vertex)
-        alg += 20 * (int64_t)n + (want_frontier ? ((int64_t)n + 7) / 8 : 0);
+        // (with the frontier wanted: a mask bit per vertex); each counted
+        // atomic is a read-modify-write of 4 bytes
+        alg += 20 * (int64_t)n + (want_frontier ? ((int64_t)n + 7) / 8 : 0) + (atomics > 0 ? 8 * atomics : 0);
         // the frontier list, and its total degree which decides the next
         // iteration's pass, are built from the mask only while a sparse pass is
         // still possible: every changed vertex has at least one entry, and at
@@ -830,6 +740,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         if (stats && ti < FASTSV_TRACE_ITERS) {
             stats->changed[ti] = changed;
             stats->sparse[ti] = sparse ? 1 : 0;
+            stats->pushed[ti] = sparse ? prev_edges : 0;
+            stats->atomics[ti] = atomics;
             if (timed) {
                 float a = 0, b = 0;
                 HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
@@ -858,6 +770,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             } else {
                 stats->dense_iterations++;
             }
+            if (atomics >= 0) stats->atomics_issued = std::max<int64_t>(stats->atomics_issued, 0) + atomics;
         }
         frontier_ready = list_ready;
         prev_fcnt = changed;
@@ -922,12 +835,13 @@ fastsv_opts fastsv_default_opts(void) {
     o.frontier_tau = 0.05f;
     o.validate = 0;
     o.timing = 0;
-    o.blocked = -1;
-    o.block_shift = 0;
     o.binned = -1;
     o.bin_shift = 0;
     o.sv_flags = kSvFastSV;
     o.mode = kModeJacobi;
+    o.trace = 0;
+    o.bin_span = 0;
+    o.admit_mb = 0;
     return o;
 }
 
@@ -1017,7 +931,7 @@ int cc_csr_impl(fastsv_ctx *ctx, int32_t n, int64_t nnz, const int32_t *rp, cons
     if (nnz > INT_MAX - kTileEntries) return FASTSV_EOVERFLOW;
     fastsv_opts opts = opts_in ? *opts_in : fastsv_default_opts();
     if (!opts_ok(opts, n)) return FASTSV_EINVAL;
-    if (stats) memset(stats, 0, sizeof(*stats));
+    clear_stats(stats);
     if (n == 0) return FASTSV_OK;
     if (!rp || !labels || (nnz > 0 && !col)) return FASTSV_EINVAL;
     if (f_init && opts.sv_flags != kSvFastSV) return FASTSV_EINVAL;  // the variants start from the identity
@@ -1093,10 +1007,8 @@ int fastsv_cc_edges(fastsv_ctx *ctx, int32_t n, int64_t m, const int32_t *src, c
     if (n < 0 || m < 0) return FASTSV_EINVAL;
     if (2 * m > INT_MAX - kTileEntries) return FASTSV_EOVERFLOW;
     fastsv_opts opts = opts_in ? *opts_in : fastsv_default_opts();
-    opts.blocked = 0;  // rows of the device-built CSR are not sorted
-    opts.block_shift = 0;
     if (!opts_ok(opts, n)) return FASTSV_EINVAL;
-    if (stats) memset(stats, 0, sizeof(*stats));
+    clear_stats(stats);
     if (n == 0) return FASTSV_OK;
     if (!labels || (m > 0 && (!src || !dst))) return FASTSV_EINVAL;
     const int64_t nnz = 2 * m;
@@ -1155,12 +1067,10 @@ int fastsv_cc_batch_csr(fastsv_ctx *ctx, int32_t num_graphs, int32_t total_n, in
     if (num_graphs < 0 || total_n < 0 || total_nnz < 0) return FASTSV_EINVAL;
     if (total_nnz > INT_MAX - kTileEntries) return FASTSV_EOVERFLOW;
     fastsv_opts opts = opts_in ? *opts_in : fastsv_default_opts();
-    opts.blocked = 0;  // column ids are local to each graph
-    opts.block_shift = 0;
     if (!opts_ok(opts, total_n)) return FASTSV_EINVAL;
     // per-graph termination is FastSV's Jacobi one
     if (opts.sv_flags != kSvFastSV || opts.mode != kModeJacobi) return FASTSV_EINVAL;
-    if (stats) memset(stats, 0, sizeof(*stats));
+    clear_stats(stats);
     if (num_graphs == 0) return total_n == 0 && total_nnz == 0 ? FASTSV_OK : FASTSV_EINVAL;
     if (!vtx_off || !edge_off || !rp || !iters || (total_n > 0 && !labels) || (total_nnz > 0 && !col))
         return FASTSV_EINVAL;

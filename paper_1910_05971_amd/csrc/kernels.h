@@ -40,10 +40,28 @@ __device__ __forceinline__ int wave_incl_sum(int v) {
 // read that already shows a value <= m (possibly an older one) proves the
 // atomic would change nothing: hot targets (shared roots) then cost a load
 // instead of an atomic.
-__device__ __forceinline__ void hook_row(int u, int m, const int *__restrict__ F, int *__restrict__ Fn) {
-    if (Fn[u] > m) atomicMin(Fn + u, m);
+// Returns the number of atomics issued.
+__device__ __forceinline__ int hook_row(int u, int m, const int *__restrict__ F, int *__restrict__ Fn) {
+    int na = 0;
+    if (Fn[u] > m) {
+        atomicMin(Fn + u, m);
+        ++na;
+    }
     const int x = F[u];
-    if (x != u && Fn[x] > m) atomicMin(Fn + x, m);
+    if (x != u && Fn[x] > m) {
+        atomicMin(Fn + x, m);
+        ++na;
+    }
+    return na;
+}
+
+// Adds the atomics counted by the lanes of a wave (all 64 lanes active) to
+// *atom with one atomic of the wave's own; nothing when atom is null.
+__device__ __forceinline__ void wave_add_atomics(unsigned long long *atom, int na) {
+    if (!atom) return;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) na += __shfl_xor(na, d, kWave);
+    if (lane_id() == 0 && na > 0) atomicAdd(atom, (unsigned long long)na);
 }
 
 // Apply the result m of row u: M update, then the two hooks if they can
@@ -52,28 +70,35 @@ __device__ __forceinline__ void hook_row(int u, int m, const int *__restrict__ F
 // kIota (first iteration): F = G = M = iota, so m < u is the whole filter, and
 // both hooks target u itself; a row owned by one tile is then the only writer
 // of M[u] and Fn[u] and stores them directly.
+// Returns the number of atomics issued.
 template <bool kIota>
-__device__ __forceinline__ void finish_row(int u, int m, bool shared_row, const int *__restrict__ F,
-                                           int *__restrict__ Fn, const int *__restrict__ G,
-                                           int *__restrict__ M) {
+__device__ __forceinline__ int finish_row(int u, int m, bool shared_row, const int *__restrict__ F,
+                                          int *__restrict__ Fn, const int *__restrict__ G,
+                                          int *__restrict__ M) {
     if (kIota) {
         if (m < u) {
             if (shared_row) {
                 atomicMin(M + u, m);
                 atomicMin(Fn + u, m);
-            } else {
-                M[u] = m;
-                Fn[u] = m;
+                return 2;
             }
+            M[u] = m;
+            Fn[u] = m;
         }
-        return;
+        return 0;
     }
+    int na = 0;
     int mu = M[u];
     if (m < mu) {
-        if (shared_row) atomicMin(M + u, m);
-        else M[u] = m;
+        if (shared_row) {
+            atomicMin(M + u, m);
+            ++na;
+        } else {
+            M[u] = m;
+        }
     }
-    if (m < G[u]) hook_row(u, m, F, Fn);
+    if (m < G[u]) na += hook_row(u, m, F, Fn);
+    return na;
 }
 
 // ---------------------------------------------------------------------------
@@ -205,11 +230,8 @@ __global__ void k_zero_counters(Counters *ctr) {
 //   kBaseIota / kBaseGather
 //               the same for a batch of graphs with local column ids: the
 //               global id is col + base[row]
-//   kPhase      column-blocked pass: the CSR's rows are segments (row, column
-//               block); finish = M update of the segment's row only (the
-//               hooks run afterwards from M, see k_hook_rows)
 // ---------------------------------------------------------------------------
-enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kPhase = 4, kVariant = 5 };
+enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kVariant = 5 };
 
 // Hooking of one row in a convergence-ablation variant (the flags of
 // fastsv_opts.sv_flags): m = min over N(u) of X[v], X = gf with grandparent
@@ -241,30 +263,24 @@ __device__ __forceinline__ void finish_variant(int u, int m, int flags, const in
     }
 }
 
+// Returns the number of atomics issued (the variants' are not counted).
 template <int kMode>
-__device__ __forceinline__ void finish_tile_row(int r, int m, bool shared_row, const int *__restrict__ aux,
-                                                const int *__restrict__ F, int *__restrict__ Fn,
-                                                const int *__restrict__ G, int *__restrict__ M, int vflags) {
+__device__ __forceinline__ int finish_tile_row(int r, int m, bool shared_row,
+                                               const int *__restrict__ F, int *__restrict__ Fn,
+                                               const int *__restrict__ G, int *__restrict__ M, int vflags) {
     if (kMode == kVariant) {
         finish_variant(r, m, vflags, F, Fn, G);
-    } else if (kMode == kPhase) {
-        int sr = aux[r];
-        int u = sr & 0x7fffffff;
-        bool sh = shared_row || sr < 0;
-        if (m < M[u]) {
-            if (sh) atomicMin(M + u, m);
-            else M[u] = m;
-        }
-    } else {
-        finish_row<kMode == kIota || kMode == kBaseIota>(r, m, shared_row, F, Fn, G, M);
+        return 0;
     }
+    return finish_row<kMode == kIota || kMode == kBaseIota>(r, m, shared_row, F, Fn, G, M);
 }
 
+// atom (nullable): the iteration's count of the atomics hooking issues.
 template <int kMode>
 __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     const Tile *__restrict__ tiles, int ntiles, const int *__restrict__ rp, const int *__restrict__ col,
     const int *__restrict__ aux, const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G,
-    int *__restrict__ M, int vflags) {
+    int *__restrict__ M, int vflags, unsigned long long *__restrict__ atom) {
     constexpr bool kBase = kMode == kBaseIota || kMode == kBaseGather;
     // gathered vector: G, or for a variant the one passed in aux (f or gf)
     const int *__restrict__ X = kMode == kVariant ? aux : G;
@@ -370,15 +386,17 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
         if (cnt > 0) atomicMin(&rmin[wave][row - T.r_lo], cur);
     }
     __syncthreads();
-    if (!tile_ok) return;
-    if (in_lds) {
+    if (!tile_ok) return;  // (uniform in the wave)
+    int na = 0;
+    if (in_lds) {  // (uniform in the wave)
         const int nrows = nwin - 1;
         for (int i = lane; i < nrows; i += kWave) {
             int m = rmin[wave][i];
             if (m == INT_MAX) continue;  // empty row
             bool shared_row = (i == 0 && wrow[0] < T.e0) || (i == nrows - 1 && wrow[nrows] > T.e1);
-            finish_tile_row<kMode>(T.r_lo + i, m, shared_row, aux, F, Fn, G, M, vflags);
+            na += finish_tile_row<kMode>(T.r_lo + i, m, shared_row, F, Fn, G, M, vflags);
         }
+        wave_add_atomics(atom, na);
         return;
     }
 
@@ -395,7 +413,7 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
                     first_min = cur;
                     first_closed = true;
                 } else {
-                    finish_tile_row<kMode>(row, cur, false, aux, F, Fn, G, M, vflags);  // row inside this lane
+                    na += finish_tile_row<kMode>(row, cur, false, F, Fn, G, M, vflags);  // row inside this lane
                 }
                 do { ++row; nxt = rpw(row + 1); } while (e >= nxt);
                 cur = INT_MAX;
@@ -409,130 +427,19 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     const int prevS = __shfl_up(S, 1, kWave);
     const int next_head = __shfl_down(first_is_head ? 1 : 0, 1, kWave);
     const int next_cnt = __shfl_down(cnt, 1, kWave);
-    if (cnt == 0) return;
-    if (first_closed) {
-        int m = first_min;
-        if (lane > 0 && !first_is_head) m = min(m, prevS);
-        finish_tile_row<kMode>(row0, m, rpw(row0) < T.e0, aux, F, Fn, G, M, vflags);
-    }
-    const bool ends_here = lane == kWave - 1 || next_cnt == 0 || next_head;
-    if (ends_here) {
-        bool shared_row = rpw(row) < T.e0 || rpw(row + 1) > T.e1;
-        finish_tile_row<kMode>(row, S, shared_row, aux, F, Fn, G, M, vflags);
-    }
-}
-
-// Hooks from the accumulated M after the column-blocked passes:
-//   if M[u] < G[u]:  Fn[u] <-min M[u],  Fn[F[u]] <-min M[u].
-// M[u] = min(M_{k-1}[u], m[u]); the older part never beats G[u] (it is at
-// least f_{k-1}[u] >= G[u]), so this is the same filter and value as hooking
-// with the fresh m[u].
-__global__ void k_hook_rows(int n, const int *__restrict__ M, const int *__restrict__ G,
-                            const int *__restrict__ F, int *__restrict__ Fn) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int stride = gridDim.x * blockDim.x;
-    for (int u = i; u < n; u += stride) {
-        int m = M[u];
-        if (m < G[u]) hook_row(u, m, F, Fn);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Column-blocked layout (built once per solve for large graphs with sorted
-// rows).  Column block b holds the vertices [b W, (b+1) W).  The entries are
-// regrouped, stably, by block: block-major, then source tile, then row.  A
-// segment is the run of one row's entries inside one source tile and one
-// block; block b's segments form a CSR over its region of cb_col.  A dense
-// iteration then runs one pass per block, whose gathers stay inside a
-// W-vertex slice of G that fits in L2, and combines the per-segment minima in
-// M.  A segment whose row also has entries in another source tile is flagged
-// (sign bit of seg_row): its M update is atomic.
-// ---------------------------------------------------------------------------
-// Row walk shared by the two preparation passes: for lane entries
-// [a, a+cnt), the row of each entry, its block, and whether it starts a segment.
-struct PrepLane {
-    int row[kPerLane];
-    int blk[kPerLane];
-    bool head[kPerLane];
-};
-
-__device__ __forceinline__ void prep_lane(const Tile &T, const int *__restrict__ rp, const int *__restrict__ col,
-                                          const int *wrow, bool in_lds, int a, int cnt, int wshift, PrepLane &P,
-                                          int &unsorted) {
-    auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
-    const int lane = lane_id();
-    int c[kPerLane];
-#pragma unroll
-    for (int j = 0; j < kPerLane; ++j) c[j] = j < cnt ? col[a + j] : 0;
-    // column id of the entry before a (previous lane's last entry)
-    int prev_c = __shfl_up(c[kPerLane - 1], 1, kWave);
-    int row = 0, nxt = 0;
     if (cnt > 0) {
-        int lo = T.r_lo, hi = T.r_hi;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (rpw(mid) <= a) lo = mid;
-            else hi = mid - 1;
+        if (first_closed) {
+            int m = first_min;
+            if (lane > 0 && !first_is_head) m = min(m, prevS);
+            na += finish_tile_row<kMode>(row0, m, rpw(row0) < T.e0, F, Fn, G, M, vflags);
         }
-        row = lo;
-        nxt = rpw(row + 1);
-    }
-    int pc = prev_c;
-#pragma unroll
-    for (int j = 0; j < kPerLane; ++j) {
-        P.head[j] = false;
-        P.blk[j] = 0;
-        P.row[j] = row;
-        if (j < cnt) {
-            int e = a + j;
-            while (e >= nxt) { ++row; nxt = rpw(row + 1); }
-            int b = c[j] >> wshift;
-            b = b < 0 ? 0 : (b >= kMaxBlocks ? kMaxBlocks - 1 : b);  // only out-of-range ids get clamped
-            bool row_start = e == rpw(row);
-            bool tile_start = (lane == 0 && j == 0);
-            P.head[j] = tile_start || row_start || (pc >> wshift) != b;
-            if (!tile_start && !row_start && pc > c[j]) unsorted = 1;
-            P.row[j] = row;
-            P.blk[j] = b;
-            pc = c[j];
+        const bool ends_here = lane == kWave - 1 || next_cnt == 0 || next_head;
+        if (ends_here) {
+            bool shared_row = rpw(row) < T.e0 || rpw(row + 1) > T.e1;
+            na += finish_tile_row<kMode>(row, S, shared_row, F, Fn, G, M, vflags);
         }
     }
-}
-
-// Pass 1: per (block, source tile) counts of entries and segments, block-major.
-__global__ __launch_bounds__(kWave) void k_cb_count(const Tile *__restrict__ tiles, int ntiles,
-                                                    const int *__restrict__ rp, const int *__restrict__ col,
-                                                    int wshift, int nblk, int *__restrict__ cnt_e,
-                                                    int *__restrict__ cnt_s, int *__restrict__ flags) {
-    __shared__ int win[kRowWin];
-    __shared__ int h_e[kMaxBlocks], h_s[kMaxBlocks];
-    const int t = blockIdx.x;
-    const int lane = lane_id();
-    const Tile T = tiles[t];
-    const int nwin = T.r_hi - T.r_lo + 2;
-    const bool in_lds = nwin <= kRowWin;
-    if (in_lds)
-        for (int i = lane; i < nwin; i += kWave) win[i] = rp[T.r_lo + i];
-    for (int b = lane; b < nblk; b += kWave) { h_e[b] = 0; h_s[b] = 0; }
-    __syncthreads();
-    const int a = T.e0 + lane * kPerLane;
-    const int cnt = max(0, min(kPerLane, T.e1 - a));
-    PrepLane P;
-    int unsorted = 0;
-    prep_lane(T, rp, col, win, in_lds, a, cnt, wshift, P, unsorted);
-#pragma unroll
-    for (int j = 0; j < kPerLane; ++j) {
-        if (j < cnt) {
-            atomicAdd(&h_e[P.blk[j]], 1);
-            if (P.head[j]) atomicAdd(&h_s[P.blk[j]], 1);
-        }
-    }
-    if (unsorted) atomicOr(flags, 1);
-    __syncthreads();
-    for (int b = lane; b < nblk; b += kWave) {
-        cnt_e[(int64_t)b * ntiles + t] = h_e[b];
-        cnt_s[(int64_t)b * ntiles + t] = h_s[b];
-    }
+    wave_add_atomics(atom, na);
 }
 
 // Exclusive scan of int32 (totals below 2^31): block-local scans of 4096
@@ -607,128 +514,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const int *__restric
         int64_t k = base + i;
         if (k < len) y[k] = run;
         run += v[i];
-    }
-}
-
-// Block bases: entries of block b start at cbb[b] (4-entry aligned), its
-// segments at sbb[b]; tb[b] = first phase tile of block b.  Also writes the
-// per-block sentinel of the segment pointer array.  Single thread.
-__global__ void k_cb_bases(const int *__restrict__ off_e, const int *__restrict__ off_s, int ntiles, int nblk,
-                           int nnz, const int *__restrict__ total_s, CbInfo *__restrict__ info) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int base = 0, tiles = 0;
-    for (int b = 0; b < nblk; ++b) {
-        int start = off_e[(int64_t)b * ntiles];
-        int end = b + 1 < nblk ? off_e[(int64_t)(b + 1) * ntiles] : nnz;
-        int len = end - start;
-        info->cbb[b] = base;
-        info->len[b] = len;
-        info->sbb[b] = off_s[(int64_t)b * ntiles];
-        info->tb[b] = tiles;
-        tiles += (len + kTileEntries - 1) / kTileEntries;
-        base += (len + 3) & ~3;
-    }
-    info->cbb[nblk] = base;
-    info->sbb[nblk] = *total_s;
-    info->tb[nblk] = tiles;
-}
-
-// Pass 2: stable scatter of entries into cb_col and of segment heads into
-// seg_ptr / seg_row.
-__global__ __launch_bounds__(kWave) void k_cb_scatter(const Tile *__restrict__ tiles, int ntiles,
-                                                      const int *__restrict__ rp, const int *__restrict__ col,
-                                                      int wshift, int nblk, const int *__restrict__ off_e,
-                                                      const int *__restrict__ off_s, const CbInfo *__restrict__ info,
-                                                      int *__restrict__ cb_col, int *__restrict__ seg_ptr,
-                                                      int *__restrict__ seg_row) {
-    __shared__ int win[kRowWin];
-    __shared__ unsigned short pe[kWave][kMaxBlocks];  // per-lane entry counts -> exclusive prefix over lanes
-    __shared__ unsigned short ps[kWave][kMaxBlocks];  // per-lane head counts  -> exclusive prefix over lanes
-    const int t = blockIdx.x;
-    const int lane = lane_id();
-    const Tile T = tiles[t];
-    const int nwin = T.r_hi - T.r_lo + 2;
-    const bool in_lds = nwin <= kRowWin;
-    if (in_lds)
-        for (int i = lane; i < nwin; i += kWave) win[i] = rp[T.r_lo + i];
-    for (int b = 0; b < nblk; ++b) { pe[lane][b] = 0; ps[lane][b] = 0; }
-    __syncthreads();
-    const int a = T.e0 + lane * kPerLane;
-    const int cnt = max(0, min(kPerLane, T.e1 - a));
-    PrepLane P;
-    int unsorted = 0;
-    prep_lane(T, rp, col, win, in_lds, a, cnt, wshift, P, unsorted);
-    int lre[kPerLane], lrs[kPerLane];
-#pragma unroll
-    for (int j = 0; j < kPerLane; ++j) {
-        if (j < cnt) {
-            lre[j] = pe[lane][P.blk[j]]++;
-            lrs[j] = P.head[j] ? ps[lane][P.blk[j]]++ : 0;
-        }
-    }
-    __syncthreads();
-    // exclusive prefix over lanes, one block column per lane
-    for (int b = lane; b < nblk; b += kWave) {
-        int re = 0, rs = 0;
-        for (int l = 0; l < kWave; ++l) {
-            int xe = pe[l][b], xs = ps[l][b];
-            pe[l][b] = (unsigned short)re;
-            ps[l][b] = (unsigned short)rs;
-            re += xe;
-            rs += xs;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kPerLane; ++j) {
-        if (j < cnt) {
-            const int b = P.blk[j];
-            const int64_t k = (int64_t)b * ntiles + t;
-            const int pos = off_e[k] - off_e[(int64_t)b * ntiles] + info->cbb[b] + pe[lane][b] + lre[j];
-            cb_col[pos] = col[a + j];
-            if (P.head[j]) {
-                const int sp = off_s[k] + ps[lane][b] + lrs[j];
-                const int u = P.row[j];
-                const bool shared = rp[u] < T.e0 || rp[u + 1] > T.e1;
-                seg_ptr[sp + b] = pos;
-                seg_row[sp] = shared ? (u | (int)0x80000000) : u;
-            }
-        }
-    }
-}
-
-__global__ void k_cb_sentinels(int nblk, const CbInfo *__restrict__ info, int *__restrict__ seg_ptr) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < nblk) seg_ptr[info->sbb[b + 1] + b] = info->cbb[b] + info->len[b];
-}
-
-// Phase tile table: for segment s of block b (local index r), the tiles of
-// block b whose first / last entry lies in the segment.
-__global__ void k_cb_tiles(int nblk, const CbInfo *__restrict__ info, const int *__restrict__ seg_ptr,
-                           Tile *__restrict__ tiles) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= info->sbb[nblk]) return;
-    int lo = 0, hi = nblk - 1;  // block of s: last b with sbb[b] <= s
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (info->sbb[mid] <= s) lo = mid;
-        else hi = mid - 1;
-    }
-    const int b = lo;
-    const int r = s - info->sbb[b];
-    const int *rpb = seg_ptr + info->sbb[b] + b;
-    const int base = info->cbb[b], end = base + info->len[b];
-    const int st = rpb[r], en = rpb[r + 1];
-    Tile *tb = tiles + info->tb[b];
-    for (int t = (st - base) / kTileEntries; t <= (en - 1 - base) / kTileEntries; ++t) {
-        int t0 = base + t * kTileEntries;
-        int last = min(t0 + kTileEntries, end) - 1;
-        if (t0 >= st && t0 < en) {
-            tb[t].e0 = t0;
-            tb[t].e1 = last + 1;
-            tb[t].r_lo = r;
-        }
-        if (last >= st && last < en) tb[t].r_hi = r;
     }
 }
 
@@ -901,7 +686,10 @@ __global__ __launch_bounds__(kGpThreads) void k_frontier_from_mask(int n, const 
 }
 
 __global__ void k_zero_iter_counters(IterCounters *c) {
-    if (threadIdx.x == 0) c->packed = 0ull;
+    if (threadIdx.x == 0) {
+        c->packed = 0ull;
+        c->atomics = 0ull;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -935,7 +723,7 @@ __global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
     const int *__restrict__ frontier, const int *__restrict__ eoff, int fcnt_arg, int total_arg,
     const IterCounters *__restrict__ counts, const int *__restrict__ rp, const int *__restrict__ col,
     const int *__restrict__ vbase, const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G,
-    int *__restrict__ M, const int *__restrict__ skip_mark, int skip_val) {
+    int *__restrict__ M, const int *__restrict__ skip_mark, int skip_val, unsigned long long *__restrict__ atom) {
     __shared__ int s_range[2];
     __shared__ int s_off[kPushSlots + 1];
     __shared__ int s_row[kPushSlots + 1];
@@ -949,6 +737,7 @@ __global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
         fcnt = (int)(pk >> 32);
         total = (int)(pk & 0xffffffffull);
     }
+    int na = 0;
     for (int chunk = blockIdx.x; (int64_t)chunk * kPushSlots < total; chunk += gridDim.x) {
         const int s0 = chunk * kPushSlots;
         const int s1 = min(s0 + kPushSlots, total);
@@ -1005,9 +794,11 @@ __global__ __launch_bounds__(kPushThreads) void k_hook_sparse(
             // and no hook follows), so it stays a load
             if (val >= M[u]) continue;
             int old = atomicMin(M + u, val);
-            if (val < old && val < G[u]) hook_row(u, val, F, Fn);
+            ++na;
+            if (val < old && val < G[u]) na += hook_row(u, val, F, Fn);
         }
     }
+    wave_add_atomics(atom, na);
 }
 
 
@@ -1294,16 +1085,44 @@ __device__ __forceinline__ int find_owner(const int *__restrict__ off, int count
     return lo;
 }
 
-// Per resident graph (pool base slot_vb[k]): changed in this step?  and the
-// total degree of its frontier, which is then reset for the next step.
-__global__ void k_srv_status(int nslots, const int *__restrict__ slot_vb, const int *__restrict__ lastk, int step,
-                             int *__restrict__ gedge, int *__restrict__ out_flag, int *__restrict__ out_edges) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nslots) return;
-    const int vb = slot_vb[k];
-    out_flag[k] = lastk[vb] == step;
-    out_edges[k] = gedge[vb];
-    gedge[vb] = 0;
+// End of a serving step for every resident graph k (run[k]): whether it
+// changed in this step and the total degree of its next frontier go straight
+// to the host (flag and edge buffers in page-locked memory), and a graph that
+// converged in this step, or was cancelled, leaves: its local labels go to
+// the page-locked out buffer at its pool positions (not for a cancelled one)
+// and its n + 1 pool vertices return to the neutral state (f = gf = mngf =
+// vbase = u, lastk = 0; vbase = u keeps every free vertex a run of its own
+// for the grandparent pass's per-graph sums).  Block b works on graph
+// find_owner(blk_off, nrun, b), vertices [c * kSettleChunk, (c + 1) *
+// kSettleChunk) with c = b - blk_off[k].  The flag is read from lastk[vb],
+// which the reset of vertex vb may set to 0 meanwhile; either value tells a
+// graph that converged (its lastk[vb] is below the step) apart from one that
+// changed.
+__global__ __launch_bounds__(256) void k_srv_settle(int nrun, const SrvRun *__restrict__ run,
+                                                    const int *__restrict__ blk_off, int step,
+                                                    int *__restrict__ lastk, int *__restrict__ gedge,
+                                                    int *__restrict__ h_flag, int *__restrict__ h_edges,
+                                                    int *__restrict__ h_out, int *__restrict__ F0,
+                                                    int *__restrict__ F1, int *__restrict__ G, int *__restrict__ M,
+                                                    int *__restrict__ vbase) {
+    const int k = find_owner(blk_off, nrun, blockIdx.x);
+    const int c = blockIdx.x - blk_off[k];
+    const SrvRun r = run[k];
+    const bool changed = !r.cancel && lastk[r.vb] == step;
+    if (c == 0 && threadIdx.x == 0) {
+        h_flag[k] = changed ? 1 : 0;
+        h_edges[k] = gedge[r.vb];
+        gedge[r.vb] = 0;
+    }
+    if (changed) return;
+    const int end = min((c + 1) * kSettleChunk, r.n + 1);
+    for (int i = c * kSettleChunk + threadIdx.x; i < end; i += blockDim.x) {
+        const int u = r.vb + i;
+        if (i < r.n && !r.cancel) h_out[u] = G[u] - r.vb;
+        F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
+        vbase[u] = u;
+        lastk[u] = 0;
+    }
 }
 
 // Tiles of the graphs that run the dense pass in this step, copied from their
@@ -1395,23 +1214,6 @@ __global__ void k_srv_tiles(int nnew, const SrvNew *__restrict__ desc, const int
             }
             if (last >= s && last < e) tb[t].r_hi = r;
         }
-    }
-}
-
-// Retirement: local labels of finished graphs into the staging buffer (at
-// s_rp of their descriptor) and their vertex range back to the neutral state.
-__global__ void k_srv_retire(int nret, const SrvNew *__restrict__ desc, const int *__restrict__ row_off,
-                             int *__restrict__ out, int *__restrict__ F0, int *__restrict__ F1, int *__restrict__ G,
-                             int *__restrict__ M, int *__restrict__ lastk) {
-    const int total = row_off[nret];
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
-        const int k = find_owner(row_off, nret, x);
-        const SrvNew d = desc[k];
-        const int i = x - row_off[k];  // 0 .. n (n is the extra vertex)
-        const int u = d.vb + i;
-        if (i < d.n) out[d.s_rp + i] = G[u] - d.vb;
-        F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
-        lastk[u] = 0;
     }
 }
 

@@ -3,37 +3,39 @@
 // Resident graphs share one device pool and advance together: every step is
 // one iteration of Algorithm 3 (dense pull over the resident graphs' tiles or
 // sparse push over the frontier, then the grandparent pass) for all of them.
-// A graph starts with the step after its placement (see 2. below); it retires
-// after the first step in which none of its grandparents changed (the
-// termination test of Sec. 3.4 applied to that graph alone).  Ids in f and gf
-// are pool-global, so resident graphs never exchange values and each one
-// follows exactly the iterates it would follow when solved alone.
+// A graph leaves at the end of the first step in which none of its
+// grandparents changed (the termination test of Sec. 3.4 applied to that
+// graph alone); its labels reach the caller when that step returns.  Ids in f
+// and gf are pool-global, so resident graphs never exchange values and each
+// one follows exactly the iterates it would follow when solved alone.
 //
 // Admission is first-come first-served and by footprint: a request waits
 // until a slot, n+1 pool vertices and nnz pool entries are free.
 //
 // One step: the iteration runs on the server's stream with a single host
 // synchronisation, and admission runs beside it on two copy streams:
-//   0. graphs placed by the previous step join the running set (the stream
-//      waits for their placement); vertex, entry and tile ranges retired by
-//      the previous step return to their allocators
-//   1. graphs found converged by the previous step: labels out to staging,
-//      vertex range back to the neutral state (one launch for all of them)
-//   2. admission of up to about kSrvStepAdmitBytes of requests: one placement
+//   0. graphs whose admission copies have completed (polled with events)
+//      join the running set; vertex, entry and tile ranges freed by the
+//      previous step return to their allocators
+//   1. admission of up to about kSrvStepAdmitBytes of requests: one placement
 //      launch on the copy stream reads the row pointers and small column
 //      arrays in place from page-locked host memory (pageable ones are staged
 //      by DMA first), large or pageable column arrays go by DMA on the second
-//      copy stream, and the tiles are built.  The admitted graphs run from the
-//      next step on (the one after while requests are still waiting, so that
-//      the copy streams stay a step ahead), or from this one when nothing
-//      else is resident.
-//   3. hooking, decided per graph: the dense pull over the graph's resident
+//      copy stream, and the tiles are built.  Small admissions with nothing
+//      waiting behind them run in this step already (the step's stream waits
+//      for their placement); the others start at the first step after their
+//      copies have completed, so that a long copy never holds up a step.
+//   2. hooking, decided per graph: the dense pull over the graph's resident
 //      tiles in its first iteration and whenever its frontier (total degree of
 //      the grandparents that changed in the previous step) exceeds
 //      frontier_tau * nnz; otherwise the sparse push from its frontier (the
 //      push skips the graphs that run dense; frontier size read on the device)
-//   4. grandparent pass over the pool, per graph: changed or not, and the
-//      degree sum of its new frontier.
+//   3. grandparent pass over the pool, per graph: changed or not, and the
+//      degree sum of its new frontier
+//   4. settle pass: the per-graph flags and frontier sizes go straight to
+//      page-locked host memory, and every graph that converged (or was
+//      cancelled) writes its labels there too and returns its vertex range to
+//      the neutral state, all in the same step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,22 +65,25 @@ struct Request {
     int32_t *iters_out;
 };
 
-// kStaged: placed (or being placed) on the copy stream, runs from its start step
-enum SlotState : int { kFree = 0, kRunning = 1, kRetiring = 2, kStaged = 3 };
+// kStaged: placed (or being placed) on the copy streams; runs from the first
+// step after its copies have completed
+enum SlotState : int { kFree = 0, kRunning = 1, kStaged = 3 };
 
 // pinned requests at least this large have their column ids copied by the DMA
 // engine straight into the pool; smaller ones are read by the placement kernel
 constexpr int64_t kSrvDmaMinEntries = 1 << 18;
-// bytes of graph data admitted per step (once at least one graph is admitted):
-// a step's transfers then take about as long as its compute, and the copy
-// stream works on the next graphs while the resident ones iterate
+// default bytes of graph data admitted per step (once at least one graph is
+// admitted; opts.admit_mb): a step's transfers then take about as long as its
+// compute, and the copy stream works on the next graphs while the resident
+// ones iterate
 constexpr int64_t kSrvStepAdmitBytes = int64_t(128) << 20;
-// while requests are still waiting after a step's admission (a backlog), the
-// admitted graphs start two steps later instead of one, so that the copy
-// streams always hold the next step's transfers as well; kSrvGens admission
-// generations (events and host buffers) are then in flight at once
-constexpr int kSrvBacklogDepth = 2;
-constexpr int kSrvGens = kSrvBacklogDepth + 1;
+// admissions of at most this many bytes, with no DMA and no request waiting
+// behind them, run in the step that admits them
+constexpr int64_t kSrvSameStepBytes = int64_t(4) << 20;
+// admission generations (events and host buffers) in flight at once: a
+// generation's buffers are reused kSrvGens steps later, after its placement
+// stream work has completed
+constexpr int kSrvGens = 8;
 
 struct Slot {
     int state = kFree;
@@ -87,8 +92,9 @@ struct Slot {
     int64_t nnz = 0;
     int vb = 0, eb = 0, tb = 0, ntiles = 0;
     int64_t fedge = 0;  // frontier degree sum after its last iteration
-    int admit_step = 0, done_step = 0;  // admit_step: the step of its first iteration
-    int gen = 0;                         // admission generation while staged
+    int admit_step = 0;  // the step of its first iteration
+    int gen = 0;         // admission generation while staged
+    bool cancel = false;  // cancelled: leaves at the next step that settles it
     int32_t *labels_out = nullptr;
     int32_t *iters_out = nullptr;
 };
@@ -96,10 +102,28 @@ struct Slot {
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct PoolLayout {
-    size_t rp, col, F0, F1, G, M, vbase, lastk, frontier, eoff, tiles, ctr, slot_vb, slot_n, flags, stage, desc,
-        chunks, off_b, out, desc_ret, off_ret, step_tiles, gmode, gedge, out_edges, desc_dense, off_dense, srcs,
-        total;
+    size_t rp, col, F0, F1, G, M, vbase, lastk, frontier, eoff, tiles, ctr, stage, desc, chunks, off_b, step_tiles,
+        gmode, gedge, stepbuf, srcs, total;
 };
+
+// The per-step descriptor, copied to the device in one transfer: the resident
+// graphs (SrvRun) and the settle pass's block offsets, the graphs running the
+// dense pass (SrvNew as k_srv_dense_tiles reads it) and their tile offsets.
+struct StepLayout {
+    size_t run, blk_off, dense, off_dense, total;
+};
+
+inline StepLayout step_layout(int64_t S) {
+    StepLayout L{};
+    size_t p = 0;
+    auto take = [&](size_t b) { size_t o = p; p += (b + 15) & ~size_t(15); return o; };
+    L.run = take(sizeof(SrvRun) * (size_t)S);
+    L.blk_off = take(sizeof(int) * (size_t)(S + 1));
+    L.dense = take(sizeof(SrvNew) * (size_t)S);
+    L.off_dense = take(sizeof(int) * (size_t)(S + 1));
+    L.total = p;
+    return L;
+}
 
 // Placement chunks one step can need: every admitted graph's vertex slots and
 // column ids, cut into kPlaceChunk items (at most S graphs, V + S vertex slots
@@ -128,22 +152,14 @@ PoolLayout pool_layout(int64_t V, int64_t E, int64_t T, int64_t S) {
     L.eoff = take(v4);
     L.tiles = take(sizeof(Tile) * (size_t)T);
     L.ctr = take(sizeof(Counters));
-    L.slot_vb = take(sizeof(int) * (size_t)S);
-    L.slot_n = take(sizeof(int) * (size_t)S);
-    L.flags = take(sizeof(int) * (size_t)S);
     L.stage = take(sizeof(int) * (size_t)(V + 1 + E));
     L.desc = take(sizeof(SrvNew) * (size_t)S);
     L.chunks = take(sizeof(PlaceChunk) * (size_t)max_place_chunks(V, E, S));
     L.off_b = take(sizeof(int) * (size_t)(S + 1));
-    L.out = take(v4);
-    L.desc_ret = take(sizeof(SrvNew) * (size_t)S);
-    L.off_ret = take(sizeof(int) * (size_t)(S + 1));
     L.step_tiles = take(sizeof(Tile) * (size_t)T);
     L.gmode = take(v4);
     L.gedge = take(v4);
-    L.out_edges = take(sizeof(int) * (size_t)S);
-    L.desc_dense = take(sizeof(SrvNew) * (size_t)S);
-    L.off_dense = take(sizeof(int) * (size_t)(S + 1));
+    L.stepbuf = take(step_layout(S).total);
     L.srcs = take(sizeof(void *) * (size_t)(2 * S));
     L.total = p;
     return L;
@@ -162,33 +178,38 @@ struct fastsv_server {
     fastsv_opts opts{};
     int64_t V = 0, E = 0, T = 0;
     int S = 0;
+    int64_t admit_bytes = 0;  // graph bytes admitted per step once one graph is in
     char *pool = nullptr;
     PoolLayout L{};
-    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *slot_vb, *slot_n, *flags, *stage, *off_b,
-        *out, *off_ret, *gmode, *gedge, *out_edges, *off_dense;
+    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *stage, *off_b, *gmode, *gedge;
     PlaceChunk *chunks;
-    SrvNew *desc, *desc_ret, *desc_dense;
+    SrvNew *desc;
     const int **srcs;
     Tile *tiles, *step_tiles;
     Counters *ctr;
-    // pinned host mirrors; the admission ones rotate over kSrvGens generations,
-    // since the copy streams may still read earlier steps' while the host
-    // prepares the next (a generation's buffers are free once its graphs have
-    // started, which is at most kSrvBacklogDepth steps after their admission)
-    int *h_slot_vb = nullptr, *h_slot_n = nullptr, *h_flags = nullptr,
-        *h_off_b2[kSrvGens] = {}, *h_out = nullptr, *h_off_ret = nullptr, *h_edges = nullptr, *h_off_dense = nullptr;
+    char *stepbuf;  // device copy of the step descriptor
+    StepLayout SL{};
+    // page-locked host memory that the settle pass writes directly (device
+    // addresses in the d_ copies): labels at pool positions, per-graph flags
+    // and frontier sizes
+    int *h_out = nullptr, *h_flags = nullptr, *h_edges = nullptr;
+    int *d_out = nullptr, *d_flags = nullptr, *d_edges = nullptr;
+    char *h_step = nullptr;  // the step descriptor
+    // admission buffers, rotating over kSrvGens generations, since the copy
+    // streams may still read earlier steps' while the host prepares the next
+    int *h_off_b2[kSrvGens] = {};
     PlaceChunk *h_chunks2[kSrvGens] = {};
-    SrvNew *h_desc2[kSrvGens] = {}, *h_desc_ret = nullptr, *h_desc_dense = nullptr;
+    SrvNew *h_desc2[kSrvGens] = {};
     const int **h_srcs2[kSrvGens] = {};
     RangeAlloc va, ea, ta;
-    // ranges of graphs retired in the current step: allocatable from the next
-    // step on, when their reset (compute stream) has completed, so that the
-    // copy stream never waits for the compute stream
+    // ranges of graphs that left in the current step: allocatable from the
+    // next step on, after their reset (compute stream) has completed, so that
+    // the copy streams never wait for the compute stream
     std::vector<std::pair<int64_t, int64_t>> rel_v, rel_e, rel_t;
     std::deque<Request> queue;
     std::vector<Slot> slots;
     std::vector<int> free_slots;  // stack of free slot indices
-    std::vector<int> flag_slot;  // slot of each entry of h_flags
+    std::vector<int> run_slot;    // slot of each entry of the step's run list
     std::deque<uint64_t> done;
     int step = 0;
     uint64_t next_ticket = 1;
@@ -226,6 +247,17 @@ bool pinned(T **p, size_t count) {
            hipSuccess;
 }
 
+// Page-locked host memory that kernels write directly and the host reads
+// after a stream synchronisation: coherent (not cached on the device) and
+// mapped; *dev receives its device address.
+template <typename T>
+bool pinned_mapped(T **p, T **dev, size_t count) {
+    if (hipHostMalloc(reinterpret_cast<void **>(p), sizeof(T) * (count > 0 ? count : 1),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return false;
+    return hipHostGetDevicePointer(reinterpret_cast<void **>(dev), *p, 0) == hipSuccess && *dev;
+}
+
 }  // namespace
 
 extern "C" {
@@ -251,7 +283,11 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     s->device = ctx_device(ctx);
     s->stream = stream;
     s->opts = opts ? *opts : fastsv_default_opts();
-    if (!(s->opts.frontier_tau >= 0.0f)) { delete s; return FASTSV_EINVAL; }
+    if (!(s->opts.frontier_tau >= 0.0f) || s->opts.admit_mb < 0 || s->opts.admit_mb > 4096) {
+        delete s;
+        return FASTSV_EINVAL;
+    }
+    s->admit_bytes = s->opts.admit_mb > 0 ? (int64_t)s->opts.admit_mb << 20 : kSrvStepAdmitBytes;
     s->V = max_vertices;
     s->E = max_entries;
     s->T = max_entries / kTileEntries + max_slots;
@@ -272,29 +308,21 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     s->eoff = reinterpret_cast<int *>(p + s->L.eoff);
     s->tiles = reinterpret_cast<Tile *>(p + s->L.tiles);
     s->ctr = reinterpret_cast<Counters *>(p + s->L.ctr);
-    s->slot_vb = reinterpret_cast<int *>(p + s->L.slot_vb);
-    s->slot_n = reinterpret_cast<int *>(p + s->L.slot_n);
-    s->flags = reinterpret_cast<int *>(p + s->L.flags);
     s->stage = reinterpret_cast<int *>(p + s->L.stage);
     s->desc = reinterpret_cast<SrvNew *>(p + s->L.desc);
     s->chunks = reinterpret_cast<PlaceChunk *>(p + s->L.chunks);
     s->off_b = reinterpret_cast<int *>(p + s->L.off_b);
-    s->out = reinterpret_cast<int *>(p + s->L.out);
-    s->desc_ret = reinterpret_cast<SrvNew *>(p + s->L.desc_ret);
-    s->off_ret = reinterpret_cast<int *>(p + s->L.off_ret);
     s->step_tiles = reinterpret_cast<Tile *>(p + s->L.step_tiles);
     s->gmode = reinterpret_cast<int *>(p + s->L.gmode);
     s->gedge = reinterpret_cast<int *>(p + s->L.gedge);
-    s->out_edges = reinterpret_cast<int *>(p + s->L.out_edges);
-    s->desc_dense = reinterpret_cast<SrvNew *>(p + s->L.desc_dense);
-    s->off_dense = reinterpret_cast<int *>(p + s->L.off_dense);
+    s->stepbuf = p + s->L.stepbuf;
+    s->SL = step_layout(s->S);
     s->srcs = reinterpret_cast<const int **>(p + s->L.srcs);
     // every host buffer below is the source or target of an asynchronous copy
-    // and is written at most once per step
-    bool ok = pinned(&s->h_out, (size_t)s->V) && pinned(&s->h_desc_ret, max_slots) &&
-              pinned(&s->h_edges, max_slots) && pinned(&s->h_desc_dense, max_slots) &&
-              pinned(&s->h_off_dense, max_slots + 1) && pinned(&s->h_off_ret, max_slots + 1) &&
-              pinned(&s->h_slot_vb, max_slots) && pinned(&s->h_slot_n, max_slots) && pinned(&s->h_flags, max_slots);
+    // or of direct device writes, and is written at most once per step
+    bool ok = pinned_mapped(&s->h_out, &s->d_out, (size_t)s->V) &&
+              pinned_mapped(&s->h_flags, &s->d_flags, max_slots) &&
+              pinned_mapped(&s->h_edges, &s->d_edges, max_slots) && pinned(&s->h_step, s->SL.total);
     for (int b = 0; b < kSrvGens && ok; ++b)
         ok = pinned(&s->h_srcs2[b], 2 * (size_t)max_slots) && pinned(&s->h_desc2[b], max_slots) &&
              pinned(&s->h_chunks2[b], (size_t)max_place_chunks(s->V, s->E, s->S)) &&
@@ -319,7 +347,7 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     launch_fill(stream, (int)(s->V + 1), s->rp, 0);
     launch_init(stream, (int)s->V, s->F[0], s->F[1], s->G, s->M, 0);
     launch_fill(stream, (int)s->V, s->lastk, 0);
-    launch_fill(stream, (int)s->V, s->vbase, 0);
+    launch_fill_iota(stream, (int)s->V, s->vbase);  // a free vertex is a run of its own
     launch_fill(stream, (int)s->V, s->gmode, 0);
     launch_fill(stream, (int)s->V, s->gedge, 0);
     launch_zero_iter(stream, &s->ctr->it[0]);
@@ -339,9 +367,7 @@ void fastsv_server_destroy(fastsv_server *s) {
     if (s->cs) (void)hipStreamSynchronize(s->cs);
     if (s->ds) (void)hipStreamSynchronize(s->ds);
     if (s->pool) (void)hipFree(s->pool);
-    for (void *h : {(void *)s->h_slot_vb, (void *)s->h_slot_n, (void *)s->h_flags, (void *)s->h_out,
-                    (void *)s->h_desc_ret, (void *)s->h_off_ret, (void *)s->h_edges, (void *)s->h_desc_dense,
-                    (void *)s->h_off_dense})
+    for (void *h : {(void *)s->h_flags, (void *)s->h_out, (void *)s->h_edges, (void *)s->h_step})
         if (h) (void)hipHostFree(h);
     for (int g = 0; g < kSrvGens; ++g) {
         for (void *h : {(void *)s->h_desc2[g], (void *)s->h_chunks2[g], (void *)s->h_off_b2[g], (void *)s->h_srcs2[g]})
@@ -424,6 +450,21 @@ int fastsv_server_submit_batch(fastsv_server *s, int32_t count, const int32_t *n
     return FASTSV_OK;
 }
 
+namespace {
+
+// 1 when every copy of the admission generation has completed, 0 when some
+// is still in flight, negative on a HIP error.
+int generation_done(fastsv_server *s, int gen) {
+    for (hipEvent_t e : {s->ev_placed[gen], s->ev_dma[gen]}) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipErrorNotReady) return 0;
+        if (q != hipSuccess) return FASTSV_EHIP;
+    }
+    return 1;
+}
+
+}  // namespace
+
 int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued) {
     if (!s) return FASTSV_EINVAL;
     SRV_TRY(hipSetDevice(s->device));
@@ -434,66 +475,37 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     IterCounters *ic_front = &s->ctr->it[(step + 1) & 1];  // frontier left by the previous step
     IterCounters *ic = &s->ctr->it[step & 1];
 
-    // 0. staged graphs whose start step this is run from now on, once their
-    //    placement (copy streams) is complete
-    int nrunning = 0, nstaged = 0;
-    unsigned starting = 0;  // generations whose graphs start in this step
-    for (Slot &sl : s->slots) {
-        if (sl.state == kStaged && sl.admit_step == step) {
-            sl.state = kRunning;
-            starting |= 1u << sl.gen;
-        }
-        nrunning += sl.state == kRunning;
-        nstaged += sl.state == kStaged;
-    }
-    for (int g = 0; g < kSrvGens; ++g)
-        if (starting & (1u << g)) {
-            SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[g], 0));
-            SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[g], 0));
-        }
-    // ranges retired by the previous step (its reset finished before that
-    // step's synchronisation returned)
+    // 0. ranges freed by the previous step (their reset finished before that
+    //    step's synchronisation returned), then the staged graphs whose
+    //    admission copies have completed join
     for (auto &r : s->rel_v) s->va.release(r.first, r.second);
     for (auto &r : s->rel_e) s->ea.release(r.first, r.second);
     for (auto &r : s->rel_t) s->ta.release(r.first, r.second);
     s->rel_v.clear();
     s->rel_e.clear();
     s->rel_t.clear();
-
-    // 1. retire the graphs found converged by the previous step (their labels
-    //    reach the callers after this step's synchronisation)
-    int nret = 0, ret_rows = 0;
-    std::vector<int> retired;
-    for (int i = 0; i < s->S; ++i) {
-        Slot &sl = s->slots[i];
-        if (sl.state != kRetiring) continue;
-        s->h_desc_ret[nret] = SrvNew{sl.vb, sl.eb, sl.n, (int)sl.nnz, ret_rows, 0, 0, 0};
-        s->h_off_ret[nret] = ret_rows;
-        ret_rows += sl.n + 1;
-        retired.push_back(i);
-        ++nret;
-    }
-    if (nret > 0) {
-        s->h_off_ret[nret] = ret_rows;
-        SRV_TRY(hipMemcpyAsync(s->desc_ret, s->h_desc_ret, sizeof(SrvNew) * nret, hipMemcpyHostToDevice, st));
-        SRV_TRY(hipMemcpyAsync(s->off_ret, s->h_off_ret, sizeof(int) * (nret + 1), hipMemcpyHostToDevice, st));
-        launch_srv_retire(st, nret, ret_rows, s->desc_ret, s->off_ret, s->out, s->F[0], s->F[1], s->G, s->M,
-                          s->lastk);
-        SRV_TRY(hipGetLastError());
-        SRV_TRY(hipMemcpyAsync(s->h_out, s->out, sizeof(int) * (size_t)ret_rows, hipMemcpyDeviceToHost, st));
-        for (int j = 0; j < nret; ++j) {
-            Slot &sl = s->slots[retired[j]];
-            s->rel_v.emplace_back(sl.vb, sl.n + 1);
-            s->rel_e.emplace_back(sl.eb, sl.nnz);
-            s->rel_t.emplace_back(sl.tb, sl.ntiles);
+    int gen_state[kSrvGens];
+    for (int g = 0; g < kSrvGens; ++g) gen_state[g] = -2;  // not queried yet
+    int nrunning = 0;
+    for (Slot &sl : s->slots) {
+        if (sl.state == kStaged) {
+            int &gs = gen_state[sl.gen];
+            if (gs == -2) gs = generation_done(s, sl.gen);
+            if (gs < 0) return FASTSV_EHIP;
+            if (gs == 1) {
+                sl.state = kRunning;
+                sl.admit_step = step;
+            }
         }
+        nrunning += sl.state == kRunning;
     }
 
-    // 2. admission, placed on the copy stream while this step computes.  The
+    // 1. admission, placed on the copy streams while this step computes.  The
     //    new vertex ranges hold the same values as the neutral state the
-    //    resident graphs' whole-range kernels may touch (F = G = M = u,
+    //    resident graphs' whole-range kernels may touch (f = gf = mngf = u,
     //    lastk = 0), so the placement and those kernels cannot disturb each
-    //    other.  With nothing else resident the new graphs run in this step.
+    //    other.  A generation's host buffers are reused once its placement
+    //    stream work (which reads them) has completed.
     SrvNew *h_desc = s->h_desc2[gen];
     const int **h_srcs = s->h_srcs2[gen];
     int *h_off_b = s->h_off_b2[gen];
@@ -501,9 +513,10 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     int nnew = 0, new_rows = 0, nchunks = 0;
     int64_t staged = 0;
     std::vector<int> admitted;
-    const bool same_step = nrunning == 0 && nstaged == 0;
     int64_t admit_bytes = 0;
-    while (!s->queue.empty() && (nnew == 0 || admit_bytes < kSrvStepAdmitBytes)) {
+    bool any_dma = false;
+    if (!s->queue.empty()) SRV_TRY(hipEventSynchronize(s->ev_placed[gen]));
+    while (!s->queue.empty() && (nnew == 0 || admit_bytes < s->admit_bytes)) {
         if (s->free_slots.empty()) break;
         const int k = s->free_slots.back();
         Request &r = s->queue.front();
@@ -516,6 +529,7 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         if (tb < 0) { s->va.release(vb, r.n + 1); s->ea.release(eb, r.nnz); break; }
         s->free_slots.pop_back();
         Slot &sl = s->slots[k];
+        sl = Slot{};
         sl.state = kStaged;
         sl.ticket = r.ticket;
         sl.n = r.n;
@@ -524,8 +538,6 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         sl.eb = (int)eb;
         sl.tb = (int)tb;
         sl.ntiles = ntiles;
-        sl.fedge = 0;
-        sl.admit_step = step + 1;  // or later, decided once the step's admission is complete
         sl.gen = gen;
         sl.labels_out = r.labels_out;
         sl.iters_out = r.iters_out;
@@ -543,8 +555,10 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
             h_srcs[2 * nnew] = s->stage + d.s_rp;
             staged += r.n + 1;
         }
-        if (col_dma)
+        if (col_dma) {
             SRV_TRY(hipMemcpyAsync(s->col + eb, r.col, sizeof(int) * (size_t)r.nnz, hipMemcpyHostToDevice, s->ds));
+            any_dma = true;
+        }
         h_srcs[2 * nnew + 1] = col_dma ? nullptr : r.dcol;
         h_desc[nnew] = d;
         h_off_b[nnew] = new_rows;
@@ -571,83 +585,146 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         SRV_TRY(hipGetLastError());
         SRV_TRY(hipEventRecord(s->ev_placed[gen], cs));
         SRV_TRY(hipEventRecord(s->ev_dma[gen], s->ds));
-        if (same_step) {
+        // small admissions with nothing waiting behind them (or with nothing
+        // else to run) start now: the step waits for their placement
+        const bool now = !any_dma && (nrunning == 0 || (s->queue.empty() && admit_bytes <= kSrvSameStepBytes));
+        if (now) {
             SRV_TRY(hipStreamWaitEvent(st, s->ev_placed[gen], 0));
-            SRV_TRY(hipStreamWaitEvent(st, s->ev_dma[gen], 0));
             for (int k : admitted) {
                 s->slots[k].state = kRunning;
                 s->slots[k].admit_step = step;
             }
-        } else if (!s->queue.empty()) {
-            for (int k : admitted) s->slots[k].admit_step = step + kSrvBacklogDepth;
         }
     }
 
-    // 3./4. one iteration for every running graph
-    int ns = 0, vhigh = 0, ndense = 0, dense_tiles = 0;
-    s->flag_slot.clear();
+    // 2.-4. one iteration for every running graph, then the settle pass over
+    //    the running and the cancelled graphs
+    const StepLayout &SL = s->SL;
+    SrvRun *h_run = reinterpret_cast<SrvRun *>(s->h_step + SL.run);
+    int *h_blk = reinterpret_cast<int *>(s->h_step + SL.blk_off);
+    SrvNew *h_dense = reinterpret_cast<SrvNew *>(s->h_step + SL.dense);
+    int *h_off_dense = reinterpret_cast<int *>(s->h_step + SL.off_dense);
+    int nrun = 0, ns = 0, vhigh = 0, ndense = 0, dense_tiles = 0, blocks = 0;
+    int64_t fedge_all = 0;
+    bool any_sparse = false;
+    s->run_slot.clear();
     for (int i = 0; i < s->S; ++i) {
-        const Slot &sl = s->slots[i];
-        if (sl.state != kRunning) continue;
-        s->h_slot_vb[ns] = sl.vb;
-        s->flag_slot.push_back(i);
-        vhigh = std::max(vhigh, sl.vb + sl.n + 1);
+        Slot &sl = s->slots[i];
+        // a cancelled graph is settled once its admission copies are complete
+        const bool staged_cancel = sl.state == kStaged && sl.cancel && gen_state[sl.gen] == 1;
+        if (sl.state != kRunning && !staged_cancel) continue;
+        h_run[nrun] = SrvRun{sl.vb, sl.n, sl.cancel ? 1 : 0, 0};
+        h_blk[nrun] = blocks;
+        blocks += (sl.n + 1 + kSettleChunk - 1) / kSettleChunk;
+        s->run_slot.push_back(i);
+        ++nrun;
+        if (sl.cancel) continue;
         ++ns;
-        const bool dense = sl.admit_step == step ||
-                           (double)sl.fedge > (double)s->opts.frontier_tau * (double)sl.nnz;
+        vhigh = std::max(vhigh, sl.vb + sl.n + 1);
+        fedge_all += sl.fedge;
+        const bool dense = sl.admit_step == step || (double)sl.fedge > (double)s->opts.frontier_tau * (double)sl.nnz;
         if (dense && sl.ntiles > 0) {
-            s->h_desc_dense[ndense] = SrvNew{sl.vb, sl.eb, sl.n, (int)sl.nnz, sl.ntiles, dense_tiles, sl.tb, 0};
-            s->h_off_dense[ndense] = dense_tiles;
+            h_dense[ndense] = SrvNew{sl.vb, sl.eb, sl.n, (int)sl.nnz, sl.ntiles, dense_tiles, sl.tb, 0};
+            h_off_dense[ndense] = dense_tiles;
             ++ndense;
             dense_tiles += sl.ntiles;
+        } else if (!dense) {
+            any_sparse = true;
         }
     }
-    launch_zero_iter(st, ic);
-    if (ns > 0) {
+    if (nrun > 0) {
+        h_blk[nrun] = blocks;
+        h_off_dense[ndense] = dense_tiles;
+        // one copy of the used part of the descriptor
+        const size_t bytes = ndense > 0 ? SL.off_dense + sizeof(int) * (size_t)(ndense + 1)
+                                        : SL.blk_off + sizeof(int) * (size_t)(nrun + 1);
+        SRV_TRY(hipMemcpyAsync(s->stepbuf, s->h_step, bytes, hipMemcpyHostToDevice, st));
+        const SrvRun *d_run = reinterpret_cast<const SrvRun *>(s->stepbuf + SL.run);
+        const int *d_blk = reinterpret_cast<const int *>(s->stepbuf + SL.blk_off);
+        const SrvNew *d_dense = reinterpret_cast<const SrvNew *>(s->stepbuf + SL.dense);
+        const int *d_off_dense = reinterpret_cast<const int *>(s->stepbuf + SL.off_dense);
         int *F = s->F[(step + 1) & 1], *Fn = s->F[step & 1];
-        SRV_TRY(hipMemcpyAsync(s->slot_vb, s->h_slot_vb, sizeof(int) * ns, hipMemcpyHostToDevice, st));
-        if (ndense > 0) {
-            s->h_off_dense[ndense] = dense_tiles;
-            SRV_TRY(hipMemcpyAsync(s->desc_dense, s->h_desc_dense, sizeof(SrvNew) * ndense, hipMemcpyHostToDevice, st));
-            SRV_TRY(hipMemcpyAsync(s->off_dense, s->h_off_dense, sizeof(int) * (ndense + 1), hipMemcpyHostToDevice,
-                                   st));
-            launch_srv_dense_tiles(st, ndense, dense_tiles, s->desc_dense, s->off_dense, s->tiles, s->step_tiles,
-                                   s->gmode, step);
-            launch_dense(st, kDenseBaseGather, s->step_tiles, dense_tiles, s->rp, s->col, s->vbase, F, Fn, s->G, s->M);
-            s->st.dense_steps++;
+        if (ns > 0) {
+            launch_zero_iter(st, ic);
+            if (ndense > 0) {
+                launch_srv_dense_tiles(st, ndense, dense_tiles, d_dense, d_off_dense, s->tiles, s->step_tiles,
+                                       s->gmode, step);
+                launch_dense(st, kDenseBaseGather, s->step_tiles, dense_tiles, s->rp, s->col, s->vbase, F, Fn, s->G,
+                             s->M);
+                s->st.dense_steps++;
+            }
+            if (any_sparse) {
+                // the push loops over the frontier (of all resident graphs) with
+                // this many workgroups
+                const int64_t want = (fedge_all + kPushSlots - 1) / kPushSlots;
+                const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
+                launch_sparse_dev(st, ic_front, nb, s->frontier, s->eoff, s->rp, s->col, s->vbase, F, Fn, s->G, s->M,
+                                  s->gmode, step);
+                s->st.sparse_steps++;
+            }
+            launch_grandparent(st, vhigh, Fn, s->G, F, s->rp, s->frontier, s->eoff, ic, 1, s->lastk, step, s->vbase,
+                               s->gedge);
         }
-        launch_sparse_dev(st, ic_front, 4096, s->frontier, s->eoff, s->rp, s->col, s->vbase, F, Fn, s->G, s->M,
-                          s->gmode, step);
-        s->st.sparse_steps++;
-        launch_grandparent(st, vhigh, Fn, s->G, F, s->rp, s->frontier, s->eoff, ic, 1, s->lastk, step, s->vbase,
-                           s->gedge);
-        launch_srv_status(st, ns, s->slot_vb, s->lastk, step, s->gedge, s->flags, s->out_edges);
+        launch_srv_settle(st, nrun, blocks, d_run, d_blk, step, s->lastk, s->gedge, s->d_flags, s->d_edges, s->d_out,
+                          s->F[0], s->F[1], s->G, s->M, s->vbase);
         SRV_TRY(hipGetLastError());
-        SRV_TRY(hipMemcpyAsync(s->h_flags, s->flags, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
-        SRV_TRY(hipMemcpyAsync(s->h_edges, s->out_edges, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
     }
     SRV_TRY(hipStreamSynchronize(st));
-    for (int j = 0; j < nret; ++j) {
-        Slot &sl = s->slots[retired[j]];
-        memcpy(sl.labels_out, s->h_out + s->h_desc_ret[j].s_rp, sizeof(int) * (size_t)sl.n);
-        if (sl.iters_out) *sl.iters_out = sl.done_step - sl.admit_step + 1;
-        s->done.push_back(sl.ticket);
-        s->st.completed++;
-        sl = Slot{};
-        s->free_slots.push_back(retired[j]);
-    }
-    for (int j = 0; j < ns; ++j) {
-        Slot &sl = s->slots[s->flag_slot[j]];
-        sl.fedge = s->h_edges[j];
-        if (!s->h_flags[j]) {
-            sl.state = kRetiring;  // converged in this step; labels leave at the next step
-            sl.done_step = step;
+    int left = 0;  // graphs that left in this step
+    for (int j = 0; j < nrun; ++j) {
+        const int i = s->run_slot[j];
+        Slot &sl = s->slots[i];
+        if (!sl.cancel && s->h_flags[j]) {
+            sl.fedge = s->h_edges[j];
+            continue;
         }
+        if (!sl.cancel) {
+            // converged in this step: labels and iteration count to the caller
+            memcpy(sl.labels_out, s->h_out + sl.vb, sizeof(int) * (size_t)sl.n);
+            if (sl.iters_out) *sl.iters_out = step - sl.admit_step + 1;
+            s->done.push_back(sl.ticket);
+            s->st.completed++;
+        } else {
+            s->st.cancelled++;
+        }
+        s->rel_v.emplace_back(sl.vb, sl.n + 1);
+        s->rel_e.emplace_back(sl.eb, sl.nnz);
+        s->rel_t.emplace_back(sl.tb, sl.ntiles);
+        sl = Slot{};
+        s->free_slots.push_back(i);
+        ++left;
     }
+    (void)left;
     s->st.steps++;
-    if (n_resident) *n_resident = ns;
+    if (n_resident) {
+        int r = 0;  // admitted and not left: running or staged
+        for (const Slot &sl : s->slots) r += sl.state != kFree;
+        *n_resident = r;
+    }
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     return FASTSV_OK;
+}
+
+int fastsv_server_cancel(fastsv_server *s, uint64_t ticket) {
+    if (!s) return FASTSV_EINVAL;
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+        if (it->ticket == ticket) {
+            s->queue.erase(it);
+            s->st.cancelled++;
+            return FASTSV_OK;
+        }
+    for (Slot &sl : s->slots) {
+        if (sl.state == kFree || sl.ticket != ticket) continue;
+        if (sl.cancel) return FASTSV_OK;
+        if (sl.state == kStaged) {
+            const int g = generation_done(s, sl.gen);
+            if (g < 0) return FASTSV_EHIP;
+            if (g == 0) return FASTSV_EBUSY;  // its admission copies are still in flight
+        }
+        sl.cancel = true;
+        return FASTSV_OK;
+    }
+    return FASTSV_EINVAL;
 }
 
 int fastsv_server_poll(fastsv_server *s, uint64_t *done, int32_t cap, int32_t *n_done) {

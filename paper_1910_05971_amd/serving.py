@@ -1,9 +1,9 @@
 """Continuous-batching server (C ABI fastsv_server_*) and open-loop drivers.
 
 ``Server`` wraps one device pool.  Requests are host CSR graphs; each
-``step()`` runs one iteration of the method for every resident graph, admits
-queued graphs that fit and retires converged ones (their labels land in the
-numpy buffer handed back by ``poll()``).
+``step()`` admits queued graphs that fit, runs one iteration of the method for
+every running graph and delivers the ones that converged in it (their labels
+land in the numpy buffer handed back by ``poll()``).
 
 ``run_open_loop`` replays a request trace with scheduled arrival times against
 the server; ``run_plain`` replays it against the one-graph-per-call path
@@ -23,7 +23,8 @@ from . import binding as B
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
-                ("steps", ctypes.c_int64), ("dense_steps", ctypes.c_int64), ("sparse_steps", ctypes.c_int64)]
+                ("steps", ctypes.c_int64), ("dense_steps", ctypes.c_int64), ("sparse_steps", ctypes.c_int64),
+                ("cancelled", ctypes.c_int64)]
 
 
 def _bind(lib):
@@ -46,6 +47,8 @@ def _bind(lib):
     lib.fastsv_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fastsv_server_poll.restype = ctypes.c_int
     lib.fastsv_server_poll.argtypes = [vp, ctypes.POINTER(u64), i32, ctypes.POINTER(i32)]
+    lib.fastsv_server_cancel.restype = ctypes.c_int
+    lib.fastsv_server_cancel.argtypes = [vp, u64]
     lib.fastsv_server_get_stats.restype = ctypes.c_int
     lib.fastsv_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib._server_bound = True
@@ -58,12 +61,14 @@ def pool_bytes(max_vertices, max_entries, max_slots):
 
 class Server:
     def __init__(self, max_vertices: int, max_entries: int, max_slots: int, device: int = 0,
-                 frontier_tau: float | None = None, validate: bool = True):
+                 frontier_tau: float | None = None, validate: bool = True, admit_mb: int | None = None):
         self.lib = _bind(B.load_library())
         self.device = device
         torch.cuda.set_device(device)
         self.stream = torch.cuda.current_stream(device)
         opts = B.make_opts(frontier_tau=frontier_tau, validate=validate)
+        if admit_mb is not None:
+            opts.admit_mb = int(admit_mb)
         h = ctypes.c_void_p()
         st = self.lib.fastsv_server_create(B.context(device), int(max_vertices), int(max_entries), int(max_slots),
                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(opts),
@@ -130,6 +135,15 @@ class Server:
         if st != B.FASTSV_OK:
             raise B.FastSVError(st, "fastsv_server_step")
         return r.value, q.value
+
+    def cancel(self, ticket: int) -> int:
+        """fastsv_server_cancel: FASTSV_OK, FASTSV_EBUSY (admission copies
+        still in flight: try again after a step) or FASTSV_EINVAL (unknown or
+        already delivered).  A cancelled ticket is never reported by poll()."""
+        st = self.lib.fastsv_server_cancel(self.h, ctypes.c_uint64(ticket))
+        if st == B.FASTSV_OK:
+            self.pending.pop(ticket, None)
+        return st
 
     def poll(self):
         cap = 4096

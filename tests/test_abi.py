@@ -38,10 +38,14 @@ def test_defaults_and_sizes():
     o = binding.default_opts()
     assert o.max_iters == 0 and abs(o.frontier_tau - 0.05) < 1e-7 and o.validate == 0
     # the last fields read back as set by the library: the struct layouts agree
-    assert o.blocked == -1 and o.binned == -1 and o.bin_shift == 0 and o.sv_flags == 15 and o.mode == 0
+    assert o.binned == -1 and o.bin_shift == 0 and o.sv_flags == 15 and o.mode == 0 and o.trace == 0
     for bad in (binding.make_opts(sv_flags=16), binding.make_opts(sv_flags=-1), binding.make_opts(bin_shift=16),
                 binding.make_opts(bin_shift=7), binding.make_opts(mode=2), binding.make_opts(mode=1, sv_flags=3)):
         assert binding.workspace_bytes(1000, 5000, bad) == 0
+    bad_trace = binding.make_opts()
+    bad_trace.trace = 2
+    assert binding.workspace_bytes(1000, 5000, bad_trace) == 0
+    assert binding.workspace_bytes(1000, 5000, binding.make_opts(trace=True)) > 0
     assert binding.workspace_bytes(1000, 5000, binding.make_opts(sv_flags="sv3")) > 0
     assert binding.workspace_bytes(-1, 0) == 0
     assert binding.workspace_bytes(10, 2**31) == 0

@@ -146,3 +146,40 @@ def test_config_c4_batch(gpu_ok):
         v0, v1 = int(b.vtx_off[g]), int(b.vtx_off[g + 1])
         assert np.array_equal(lab[v0:v1], O.uf_labels(sub.n, sub.row_ptr, sub.col)), g
     _say(f"[gpu] C4 iterations={st.iterations} max per-graph={its.max()}")
+
+
+def test_trace_counts_atomics_without_changing_iterates(gpu_ok):
+    """opts.trace: the hooks' atomics are counted per iteration (their sum is
+    the total, and alg_bytes grows by 8 B per atomic); labels, iteration count
+    and changed counts are those of the untraced call.  A graph without edges
+    issues no atomic."""
+    import paper_1910_05971_amd as fs
+    cases = [(gg.rmat(15, 16, seed=61), {}), (gg.er(40000, 90000, seed=62), {"frontier_tau": 1.0}),
+             (gg.grid(200, 300, 0.55, seed=63), {"frontier_tau": 0.0}), (gg.rmat(16, 8, seed=64), {"binned": True})]
+    for g, kw in cases:
+        _say(f"[gpu] trace {g.name} {kw}")
+        rp, col = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
+        plain, sp = fs.cc_csr(rp, col, **kw)
+        traced, st = fs.cc_csr(rp, col, trace=True, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(plain, traced)
+        assert st.iterations == sp.iterations and st.changed_list() == sp.changed_list()
+        assert sp.atomics_issued == -1 and all(a == -1 for a in sp.atomics_list())
+        per = st.atomics_list()
+        assert all(a >= 0 for a in per) and sum(per) == st.atomics_issued > 0
+        assert st.alg_bytes == sp.alg_bytes + 8 * st.atomics_issued
+        assert sum(st.pushed_list()) == st.frontier_edges == sp.frontier_edges
+        assert all(p == 0 for p, s in zip(st.pushed_list(), st.sparse_list()) if not s)
+    # vertices without edges: one iteration, nothing hooked
+    rp0 = torch.zeros(1001, dtype=torch.int32, device="cuda")
+    col0 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    _, s0 = fs.cc_csr(rp0, col0, trace=True)
+    assert s0.iterations == 1 and s0.atomics_issued == 0
+    # the batch entry counts too
+    b = gg.batch(64, seed=65, max_n=4096)
+    vo, eo, rpb, colb = _batch_to_dev(b)
+    lab1, it1, sb1 = fs.cc_batch_csr(vo, eo, rpb, colb)
+    lab2, it2, sb2 = fs.cc_batch_csr(vo, eo, rpb, colb, trace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(lab1, lab2) and torch.equal(it1, it2)
+    assert sb2.atomics_issued == sum(sb2.atomics_list()) > 0 and sb1.atomics_issued == -1

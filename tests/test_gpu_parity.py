@@ -178,33 +178,6 @@ def test_sparse_rows_wide_windows(gpu_ok):
     assert st.num_bins == 256 and st.bin_fused_first == 1
 
 
-def test_blocked_passes_trajectories(gpu_ok):
-    # column-blocked dense passes forced on moderate graphs with many blocks
-    import paper_1910_05971_amd as fs
-    graphs = [(gg.rmat(14, 16, seed=51), 8), (gg.er(30000, 120000, seed=52), 9),
-              (gg.grid(120, 150, 0.6, seed=53), 9), (gg.rmat(16, 8, seed=54), 10)]
-    for g, shift in graphs:
-        ref = check_graph(g, taus=(0.0, 0.05), trajectory=True, blocked=True, block_shift=shift)
-        rp, col = to_dev(g)
-        _, st = solve(rp, col, frontier_tau=0.0, blocked=True, block_shift=shift)
-        assert st.blocked_prepared == 1
-        assert st.blocked_iterations == max(0, ref.iterations - 1), (g.name, st.blocked_iterations)
-
-
-def test_blocked_unsorted_rows_fall_back(gpu_ok):
-    g = gg.er(20000, 60000, seed=55)
-    rng = np.random.default_rng(3)
-    col = g.col.copy()
-    for u in range(g.n):
-        a, b = g.row_ptr[u], g.row_ptr[u + 1]
-        col[a:b] = rng.permutation(col[a:b])
-    g2 = gg.Graph("er_unsorted", g.n, g.row_ptr, col, g.m_eff)
-    check_graph(g2, taus=(0.0,), trajectory=True, blocked=True, block_shift=9)
-    rp_d, col_d = to_dev(g2)
-    _, st = solve(rp_d, col_d, frontier_tau=0.0, blocked=True, block_shift=9)
-    assert st.blocked_prepared == 1 and st.blocked_iterations == 0
-
-
 def test_binned_passes_trajectories(gpu_ok):
     # binned dense passes forced on moderate graphs with narrow bins: many bins,
     # bins shorter than one block-wide span of the dense pass (32768 entries),
@@ -363,13 +336,11 @@ def test_config_c2_rmat(gpu_ok):
     rp, col = to_dev(g)
     want = O.uf_labels(g.n, g.row_ptr, g.col)
     assert int(np.count_nonzero(want == np.arange(g.n))) == ref["components"]
-    for tau, blocked, binned in ((0.0, False, False), (0.05, None, None), (0.05, True, False), (0.0, False, True),
-                                 (1.0, False, True)):
-        got, st = solve(rp, col, frontier_tau=tau, blocked=blocked, binned=binned)
-        _say(f"[gpu] C2 tau={tau} blocked={blocked} binned={binned} iterations={st.iterations} "
-             f"changed={st.changed_list()} blocked_iterations={st.blocked_iterations} "
-             f"binned_iterations={st.binned_iterations}")
-        assert np.array_equal(got, want), f"C2 tau={tau} blocked={blocked} binned={binned}"
-        assert st.iterations == ref["iterations"], (tau, blocked, binned, st.iterations)
-        assert st.changed_list() == ref["changed"], (tau, blocked, binned, st.changed_list())
+    for tau, binned in ((0.0, False), (0.05, None), (0.0, True), (1.0, True)):
+        got, st = solve(rp, col, frontier_tau=tau, binned=binned)
+        _say(f"[gpu] C2 tau={tau} binned={binned} iterations={st.iterations} "
+             f"changed={st.changed_list()} binned_iterations={st.binned_iterations}")
+        assert np.array_equal(got, want), f"C2 tau={tau} binned={binned}"
+        assert st.iterations == ref["iterations"], (tau, binned, st.iterations)
+        assert st.changed_list() == ref["changed"], (tau, binned, st.changed_list())
     O.check_final(got, g.row_ptr, g.col)

@@ -176,3 +176,59 @@ def test_server_request_trace_with_rmat20(gpu_ok):
         assert got[i] is not None, i
         assert np.array_equal(got[i][0], lab), (i, g.name)
         assert got[i][1] == its, (i, g.name, got[i][1], its)
+
+
+def test_server_cancel(gpu_ok):
+    """A queued request is dropped at once; an admitted one (here the largest,
+    whose column ids go by DMA) leaves at the next step; neither is ever
+    reported, and the pool ranges they held serve later requests correctly.
+    EBUSY only while the admission copies are in flight; unknown or delivered
+    tickets are refused."""
+    import paper_1910_05971_amd as fs
+    from paper_1910_05971_amd.serving import Server
+    big = gg.rmat(18, 16, seed=81)
+    small = [gg.er(4000, 9000, seed=82 + k) for k in range(6)]
+    srv = Server(max_vertices=600_000, max_entries=12_000_000, max_slots=8)
+    t_big = srv.submit(big.row_ptr, big.col)
+    t_small = [srv.submit(g.row_ptr, g.col) for g in small]
+    assert srv.cancel(t_small[2]) == fs.FASTSV_OK  # still queued
+    assert srv.cancel(987654321) == fs.FASTSV_EINVAL
+    got = {}
+    srv.step()
+    busy = 0
+    while True:
+        st = srv.cancel(t_big)
+        if st == fs.FASTSV_OK:
+            break
+        assert st == fs.FASTSV_EBUSY
+        busy += 1
+        srv.step()
+        assert busy < 10000
+    for _ in range(10000):
+        r, q = srv.step()
+        for t, lab, its in srv.poll():
+            got[t] = (lab.copy(), its)
+        if r == 0 and q == 0:
+            break
+    assert t_big not in got and t_small[2] not in got
+    for k, t in enumerate(t_small):
+        if k == 2:
+            continue
+        lab, its = _expected(small[k])
+        assert np.array_equal(got[t][0], lab) and got[t][1] == its
+    assert srv.cancel(t_small[0]) == fs.FASTSV_EINVAL  # delivered
+    st = srv.stats()
+    assert st.cancelled == 2 and st.completed == len(small) - 1
+    # the freed ranges serve the same graphs again
+    t2 = [srv.submit(g.row_ptr, g.col) for g in [big] + small]
+    got2 = {}
+    for _ in range(10000):
+        r, q = srv.step()
+        for t, lab, its in srv.poll():
+            got2[t] = (lab.copy(), its)
+        if r == 0 and q == 0:
+            break
+    srv.close()
+    for t, g in zip(t2, [big] + small):
+        lab, its = _expected(g)
+        assert np.array_equal(got2[t][0], lab) and got2[t][1] == its, g.name
