@@ -78,20 +78,28 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
     const int64_t e0 = (int64_t)k * chunk_tiles * kTileEntries;
     const int64_t e1 = min(e0 + (int64_t)chunk_tiles * kTileEntries, nnz);
     const bool vec = (reinterpret_cast<uintptr_t>(col) & 15) == 0;
-    for (int64_t e = e0 + 4 * tid; e < e1; e += 4 * kBinThreads) {
-        if (vec && e + 4 <= e1) {
-            const v4i c = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + e));
-            if (c.x >= 0 && c.x < n) atomicAdd(&hist[bin_of(c.x, bd)], 1);
-            if (c.y >= 0 && c.y < n) atomicAdd(&hist[bin_of(c.y, bd)], 1);
-            if (c.z >= 0 && c.z < n) atomicAdd(&hist[bin_of(c.z, bd)], 1);
-            if (c.w >= 0 && c.w < n) atomicAdd(&hist[bin_of(c.w, bd)], 1);
-        } else {
-            for (int64_t f = e; f < min(e + 4, e1); ++f) {
-                const int c = col[f];
-                if (c >= 0 && c < n) atomicAdd(&hist[bin_of(c, bd)], 1);
+    // kCountLoads 16-byte loads per thread are issued before their entries are
+    // counted, so that they are in flight together
+    constexpr int kCountLoads = 8;
+    constexpr int64_t kStride = 4 * kBinThreads;
+    auto count = [&](int c) {
+        if (c >= 0 && c < n) atomicAdd(&hist[bin_of(c, bd)], 1);
+    };
+    int64_t e = e0 + 4 * tid;
+    if (vec) {
+        for (; e + (kCountLoads - 1) * kStride + 4 <= e1; e += kCountLoads * kStride) {
+            v4i c[kCountLoads];
+#pragma unroll
+            for (int q = 0; q < kCountLoads; ++q)
+                c[q] = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(col + e + q * kStride));
+#pragma unroll
+            for (int q = 0; q < kCountLoads; ++q) {
+                count(c[q].x); count(c[q].y); count(c[q].z); count(c[q].w);
             }
         }
     }
+    for (; e < e1; e += kStride)
+        for (int64_t f = e; f < min(e + 4, e1); ++f) count(col[f]);
     __syncthreads();
     const ChunkHi ch = chunk_hi(tiles, ntiles, k, chunk_tiles);
     const int markers = ch.end - ch.prev;

@@ -189,9 +189,11 @@ void launch_zero_iter(hipStream_t s, IterCounters *ic);
 // lastk (nullable): iteration of the last change per vertex, or per graph at
 // index vbase[u] when vbase is given; gedge (nullable, needs vbase): frontier
 // degree sum per graph at index vbase[u]
+// the pass covers [u_begin rounded down to a block, n)
 void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
                         int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter,
-                        const int *vbase = nullptr, int *gedge = nullptr, unsigned long long *fmask = nullptr);
+                        const int *vbase = nullptr, int *gedge = nullptr, unsigned long long *fmask = nullptr,
+                        int u_begin = 0);
 // The frontier list of the vertices marked in fmask (see k_frontier_from_mask);
 // fb ends as (count << 32 | degree sum).
 void launch_frontier_from_mask(hipStream_t s, int n, const unsigned long long *fmask, const int *rp, int *frontier,
@@ -204,9 +206,13 @@ void launch_fill_iota(hipStream_t s, int n, int *x);
 // device addresses of page-locked host memory
 void launch_srv_settle(hipStream_t s, int nrun, int blocks, const SrvRun *run, const int *blk_off, int step,
                        int *lastk, int *gedge, int *h_flag, int *h_edges, int *h_out, int *F0, int *F1, int *G,
-                       int *M, int *vbase);
-void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
-                            const Tile *pool_tiles, Tile *step_tiles, int *mark, int step);
+                       int *M, int *vbase, IterCounters *next_ic);
+// the dense pull over the resident tiles of ndense graphs (desc[k]: tile_base
+// = first resident tile, vb = graph base; tile_off = exclusive prefix of their
+// tile counts), marking each in mark[] with the step
+void launch_srv_dense(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
+                      const Tile *pool_tiles, int *mark, int step, const int *rp, const int *col, const int *vbase,
+                      const int *F, int *Fn, const int *G, int *M);
 void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
                       const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
                       int *lastk);

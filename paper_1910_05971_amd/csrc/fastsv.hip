@@ -224,19 +224,19 @@ void launch_dense(hipStream_t s, int mode, const Tile *tiles, int ntiles, const 
     switch (mode) {
         case kDenseIota:
             hipLaunchKernelGGL((k_tile_reduce<kIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M, 0,
-                               atom);
+                               atom, SrvTiles{});
             break;
         case kDenseGather:
             hipLaunchKernelGGL((k_tile_reduce<kGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G, M,
-                               0, atom);
+                               0, atom, SrvTiles{});
             break;
         case kDenseBaseIota:
             hipLaunchKernelGGL((k_tile_reduce<kBaseIota>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn, G,
-                               M, 0, atom);
+                               M, 0, atom, SrvTiles{});
             break;
         default:
             hipLaunchKernelGGL((k_tile_reduce<kBaseGather>), grid, block, 0, s, tiles, ntiles, rp, col, vbase, F, Fn,
-                               G, M, 0, atom);
+                               G, M, 0, atom, SrvTiles{});
             break;
     }
 }
@@ -275,10 +275,11 @@ void launch_zero_iter(hipStream_t s, IterCounters *ic) {
 
 void launch_grandparent(hipStream_t s, int n, const int *Fn, int *G, int *next_fn, const int *rp, int *frontier,
                         int *eoff, IterCounters *ic, int write_frontier, int *lastk, int iter, const int *vbase,
-                        int *gedge, unsigned long long *fmask) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_grandparent, dim3(grid_for(n, kGpBlockVerts)), dim3(kGpThreads), 0, s, n, Fn, G, next_fn, rp,
-                       frontier, eoff, ic, write_frontier, lastk, iter, vbase, gedge, fmask);
+                        int *gedge, unsigned long long *fmask, int u_begin) {
+    u_begin -= u_begin % kGpBlockVerts;
+    if (n <= u_begin) return;
+    hipLaunchKernelGGL(k_grandparent, dim3(grid_for(n - u_begin, kGpBlockVerts)), dim3(kGpThreads), 0, s, u_begin, n,
+                       Fn, G, next_fn, rp, frontier, eoff, ic, write_frontier, lastk, iter, vbase, gedge, fmask);
 }
 
 void launch_frontier_from_mask(hipStream_t s, int n, const unsigned long long *fmask, const int *rp, int *frontier,
@@ -301,17 +302,19 @@ void launch_fill(hipStream_t s, int n, int *x, int v) {
 
 void launch_srv_settle(hipStream_t s, int nrun, int blocks, const SrvRun *run, const int *blk_off, int step,
                        int *lastk, int *gedge, int *h_flag, int *h_edges, int *h_out, int *F0, int *F1, int *G,
-                       int *M, int *vbase) {
+                       int *M, int *vbase, IterCounters *next_ic) {
     if (nrun <= 0 || blocks <= 0) return;
     hipLaunchKernelGGL(k_srv_settle, dim3(blocks), dim3(256), 0, s, nrun, run, blk_off, step, lastk, gedge, h_flag,
-                       h_edges, h_out, F0, F1, G, M, vbase);
+                       h_edges, h_out, F0, F1, G, M, vbase, next_ic);
 }
 
-void launch_srv_dense_tiles(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
-                            const Tile *pool_tiles, Tile *step_tiles, int *mark, int step) {
+void launch_srv_dense(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
+                      const Tile *pool_tiles, int *mark, int step, const int *rp, const int *col, const int *vbase,
+                      const int *F, int *Fn, const int *G, int *M) {
     if (ndense <= 0 || total_tiles <= 0) return;
-    hipLaunchKernelGGL(k_srv_dense_tiles, dim3(grid_for(total_tiles, 256, 8192)), dim3(256), 0, s, ndense, desc,
-                       tile_off, pool_tiles, step_tiles, mark, step);
+    const dim3 grid(grid_for(total_tiles, kHookWaves)), block(kWave * kHookWaves);
+    hipLaunchKernelGGL((k_tile_reduce<kSrvGather>), grid, block, 0, s, pool_tiles, total_tiles, rp, col, vbase, F, Fn,
+                       G, M, 0, (unsigned long long *)nullptr, SrvTiles{ndense, desc, tile_off, mark, step});
 }
 
 void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
@@ -488,7 +491,7 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
                                    (fl & 4) ? 1 : 0);
             else
                 hipLaunchKernelGGL((k_tile_reduce<kVariant>), grid, block, 0, stream, w.tiles, (int)ntiles, P.rp,
-                                   P.col, grand ? G : F, F, Fn, G, w.M, fl, (unsigned long long *)nullptr);
+                                   P.col, grand ? G : F, F, Fn, G, w.M, fl, (unsigned long long *)nullptr, SrvTiles{});
         }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
         launch_zero_iter(stream, ic);

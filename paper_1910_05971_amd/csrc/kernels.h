@@ -227,11 +227,25 @@ __global__ void k_zero_counters(Counters *ctr) {
 //   kIota       first iteration: G is the identity, so the gathered value is
 //               the column id itself
 //   kGather     m = min G[col]; finish = M update + hooks
+//   kSrvGather  kBaseGather over the tiles of the serving pool's dense graphs
+//               (see SrvTiles)
 //   kBaseIota / kBaseGather
 //               the same for a batch of graphs with local column ids: the
 //               global id is col + base[row]
 // ---------------------------------------------------------------------------
-enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kVariant = 5 };
+enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kVariant = 5, kSrvGather = 6 };
+
+// Tiles of the serving pool's dense graphs: wave t of the launch takes tile
+// t - off[k] of graph k = the last one with off[k] <= t (desc[k].tile_base is
+// its first resident tile), and the graph's first wave marks it in mark[] so
+// that the step's push skips its frontier.
+struct SrvTiles {
+    int ndense;
+    const SrvNew *desc;
+    const int *off;
+    int *mark;
+    int step;
+};
 
 // Hooking of one row in a convergence-ablation variant (the flags of
 // fastsv_opts.sv_flags): m = min over N(u) of X[v], X = gf with grandparent
@@ -245,6 +259,8 @@ enum Mode : int { kIota = 0, kGather = 1, kBaseIota = 2, kBaseGather = 3, kVaria
 //     smallest f[v] below it, which is m whenever m < f[u]; aggressive hooking
 //     adds Fn[u] <-min m.  (With grandparent hooking the hook condition tests
 //     f[v], not the value hooked onto: k_var_root_hook.)
+__device__ __forceinline__ int find_owner(const int *__restrict__ off, int count, int64_t x);
+
 __device__ __forceinline__ void finish_variant(int u, int m, int flags, const int *__restrict__ F,
                                                int *__restrict__ Fn, const int *__restrict__ G) {
     const bool stoch = flags & 2, aggr = flags & 4;
@@ -280,8 +296,8 @@ template <int kMode>
 __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     const Tile *__restrict__ tiles, int ntiles, const int *__restrict__ rp, const int *__restrict__ col,
     const int *__restrict__ aux, const int *__restrict__ F, int *__restrict__ Fn, const int *__restrict__ G,
-    int *__restrict__ M, int vflags, unsigned long long *__restrict__ atom) {
-    constexpr bool kBase = kMode == kBaseIota || kMode == kBaseGather;
+    int *__restrict__ M, int vflags, unsigned long long *__restrict__ atom, SrvTiles srv) {
+    constexpr bool kBase = kMode == kBaseIota || kMode == kBaseGather || kMode == kSrvGather;
     // gathered vector: G, or for a variant the one passed in aux (f or gf)
     const int *__restrict__ X = kMode == kVariant ? aux : G;
     constexpr bool kNoGather = kMode == kIota || kMode == kBaseIota;
@@ -291,7 +307,18 @@ __global__ __launch_bounds__(kWave *kHookWaves) void k_tile_reduce(
     const int lane = lane_id();
     const int t = blockIdx.x * kHookWaves + wave;
     const bool tile_ok = t < ntiles;
-    Tile T = tile_ok ? tiles[t] : Tile{0, 0, 0, -1};
+    Tile T = Tile{0, 0, 0, -1};
+    if (kMode == kSrvGather) {
+        if (tile_ok) {
+            const int k = find_owner(srv.off, srv.ndense, t);
+            const SrvNew d = srv.desc[k];
+            const int i = t - srv.off[k];
+            T = tiles[d.tile_base + i];
+            if (i == 0 && lane == 0) srv.mark[d.vb] = srv.step;
+        }
+    } else if (tile_ok) {
+        T = tiles[t];
+    }
     const int a = T.e0 + lane * kPerLane;
     const int cnt = tile_ok ? max(0, min(kPerLane, T.e1 - a)) : 0;
 
@@ -528,8 +555,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const int *__restric
 // its degree sum when a sparse iteration may follow.  Count and degree sum share one 64-bit
 // counter (count in the high half), updated once per block.
 // ---------------------------------------------------------------------------
+// The pass covers the vertices [u_begin, n); u_begin is a multiple of
+// kGpBlockVerts (the serving pool skips its unused low part).
 __global__ __launch_bounds__(kGpThreads) void k_grandparent(
-    int n, const int *__restrict__ Fn, int *__restrict__ G, int *__restrict__ next_fn,
+    int u_begin, int n, const int *__restrict__ Fn, int *__restrict__ G, int *__restrict__ next_fn,
     const int *__restrict__ rp, int *__restrict__ frontier, int *__restrict__ eoff,
     IterCounters *__restrict__ ctr, int write_frontier, int *__restrict__ lastk, int iter,
     const int *__restrict__ vbase, int *__restrict__ gedge, unsigned long long *__restrict__ fmask) {
@@ -539,7 +568,7 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
     __shared__ unsigned long long s_base;
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int base_u = blockIdx.x * kGpBlockVerts;
+    const int base_u = u_begin + blockIdx.x * kGpBlockVerts;
     bool ch[kGpPerThread];
     int deg[kGpPerThread];
 #pragma unroll
@@ -1097,14 +1126,20 @@ __device__ __forceinline__ int find_owner(const int *__restrict__ off, int count
 // kSettleChunk) with c = b - blk_off[k].  The flag is read from lastk[vb],
 // which the reset of vertex vb may set to 0 meanwhile; either value tells a
 // graph that converged (its lastk[vb] is below the step) apart from one that
-// changed.
+// changed.  It also clears next_ic, the counters the next step's
+// grandparent pass accumulates into.
 __global__ __launch_bounds__(256) void k_srv_settle(int nrun, const SrvRun *__restrict__ run,
                                                     const int *__restrict__ blk_off, int step,
                                                     int *__restrict__ lastk, int *__restrict__ gedge,
                                                     int *__restrict__ h_flag, int *__restrict__ h_edges,
                                                     int *__restrict__ h_out, int *__restrict__ F0,
                                                     int *__restrict__ F1, int *__restrict__ G, int *__restrict__ M,
-                                                    int *__restrict__ vbase) {
+                                                    int *__restrict__ vbase, IterCounters *__restrict__ next_ic) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the next step's counters (this step's push has read them already)
+        next_ic->packed = 0ull;
+        next_ic->atomics = 0ull;
+    }
     const int k = find_owner(blk_off, nrun, blockIdx.x);
     const int c = blockIdx.x - blk_off[k];
     const SrvRun r = run[k];
@@ -1122,23 +1157,6 @@ __global__ __launch_bounds__(256) void k_srv_settle(int nrun, const SrvRun *__re
         F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
         vbase[u] = u;
         lastk[u] = 0;
-    }
-}
-
-// Tiles of the graphs that run the dense pass in this step, copied from their
-// resident tile ranges into one array; their graphs are marked for the push to
-// skip.  desc[k]: tile_base = first resident tile, s_rp = tile count,
-// s_col = offset in the step array; vb = graph base.
-__global__ void k_srv_dense_tiles(int ndense, const SrvNew *__restrict__ desc, const int *__restrict__ tile_off,
-                                  const Tile *__restrict__ pool_tiles, Tile *__restrict__ step_tiles,
-                                  int *__restrict__ mark, int step) {
-    const int total = tile_off[ndense];
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
-        const int k = find_owner(tile_off, ndense, x);
-        const SrvNew d = desc[k];
-        const int i = x - tile_off[k];
-        step_tiles[x] = pool_tiles[d.tile_base + i];
-        if (i == 0) mark[d.vb] = step;
     }
 }
 

@@ -35,7 +35,8 @@
 //   4. settle pass: the per-graph flags and frontier sizes go straight to
 //      page-locked host memory, and every graph that converged (or was
 //      cancelled) writes its labels there too and returns its vertex range to
-//      the neutral state, all in the same step.
+//      the neutral state, all in the same step; it also clears the next step's
+//      counters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -102,13 +103,12 @@ struct Slot {
 inline size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct PoolLayout {
-    size_t rp, col, F0, F1, G, M, vbase, lastk, frontier, eoff, tiles, ctr, stage, desc, chunks, off_b, step_tiles,
-        gmode, gedge, stepbuf, srcs, total;
+    size_t rp, col, F0, F1, G, M, vbase, lastk, frontier, eoff, tiles, ctr, stage, adm, gmode, gedge, stepbuf, total;
 };
 
 // The per-step descriptor, copied to the device in one transfer: the resident
 // graphs (SrvRun) and the settle pass's block offsets, the graphs running the
-// dense pass (SrvNew as k_srv_dense_tiles reads it) and their tile offsets.
+// dense pass (SrvNew as the kSrvGather pull reads it) and their tile offsets.
 struct StepLayout {
     size_t run, blk_off, dense, off_dense, total;
 };
@@ -132,6 +132,26 @@ inline int64_t max_place_chunks(int64_t V, int64_t E, int64_t S) {
     return (V + S + E) / kPlaceChunk + 2 * S + 2;
 }
 
+// One admission's arrays, packed for a single host-to-device copy (16-byte
+// aligned): descriptors, source pointers, row offsets, placement chunks.
+struct AdmLayout {
+    size_t desc, srcs, off_b, chunks, total;
+};
+
+inline AdmLayout adm_layout(int64_t nnew, int64_t nchunks) {
+    auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+    AdmLayout A;
+    A.desc = 0;
+    A.srcs = al(A.desc + sizeof(SrvNew) * (size_t)nnew);
+    A.off_b = al(A.srcs + sizeof(void *) * 2 * (size_t)nnew);
+    A.chunks = al(A.off_b + sizeof(int) * (size_t)(nnew + 1));
+    A.total = A.chunks + sizeof(PlaceChunk) * (size_t)nchunks;
+    return A;
+}
+
+// the largest admission: every slot, every placement chunk the pool allows
+inline size_t adm_bytes(int64_t V, int64_t E, int64_t S) { return adm_layout(S, max_place_chunks(V, E, S)).total; }
+
 // T: tiles of one step's new graphs; the staging buffer holds the row_ptr and
 // col of all graphs admitted in one step (at most V + E ints) and the labels
 // of all graphs retired in one step (at most V ints).
@@ -153,14 +173,10 @@ PoolLayout pool_layout(int64_t V, int64_t E, int64_t T, int64_t S) {
     L.tiles = take(sizeof(Tile) * (size_t)T);
     L.ctr = take(sizeof(Counters));
     L.stage = take(sizeof(int) * (size_t)(V + 1 + E));
-    L.desc = take(sizeof(SrvNew) * (size_t)S);
-    L.chunks = take(sizeof(PlaceChunk) * (size_t)max_place_chunks(V, E, S));
-    L.off_b = take(sizeof(int) * (size_t)(S + 1));
-    L.step_tiles = take(sizeof(Tile) * (size_t)T);
+    L.adm = take(adm_bytes(V, E, S));
     L.gmode = take(v4);
     L.gedge = take(v4);
     L.stepbuf = take(step_layout(S).total);
-    L.srcs = take(sizeof(void *) * (size_t)(2 * S));
     L.total = p;
     return L;
 }
@@ -185,7 +201,7 @@ struct fastsv_server {
     PlaceChunk *chunks;
     SrvNew *desc;
     const int **srcs;
-    Tile *tiles, *step_tiles;
+    Tile *tiles;
     Counters *ctr;
     char *stepbuf;  // device copy of the step descriptor
     StepLayout SL{};
@@ -201,6 +217,9 @@ struct fastsv_server {
     PlaceChunk *h_chunks2[kSrvGens] = {};
     SrvNew *h_desc2[kSrvGens] = {};
     const int **h_srcs2[kSrvGens] = {};
+    char *h_adm2[kSrvGens] = {};  // the four arrays above packed for one copy
+    char *adm = nullptr;          // its device copy
+    bool next_ic_clean = true;    // the next step's counters were cleared by a settle pass
     RangeAlloc va, ea, ta;
     // ranges of graphs that left in the current step: allocatable from the
     // next step on, after their reset (compute stream) has completed, so that
@@ -309,15 +328,11 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     s->tiles = reinterpret_cast<Tile *>(p + s->L.tiles);
     s->ctr = reinterpret_cast<Counters *>(p + s->L.ctr);
     s->stage = reinterpret_cast<int *>(p + s->L.stage);
-    s->desc = reinterpret_cast<SrvNew *>(p + s->L.desc);
-    s->chunks = reinterpret_cast<PlaceChunk *>(p + s->L.chunks);
-    s->off_b = reinterpret_cast<int *>(p + s->L.off_b);
-    s->step_tiles = reinterpret_cast<Tile *>(p + s->L.step_tiles);
+    s->adm = p + s->L.adm;
     s->gmode = reinterpret_cast<int *>(p + s->L.gmode);
     s->gedge = reinterpret_cast<int *>(p + s->L.gedge);
     s->stepbuf = p + s->L.stepbuf;
     s->SL = step_layout(s->S);
-    s->srcs = reinterpret_cast<const int **>(p + s->L.srcs);
     // every host buffer below is the source or target of an asynchronous copy
     // or of direct device writes, and is written at most once per step
     bool ok = pinned_mapped(&s->h_out, &s->d_out, (size_t)s->V) &&
@@ -326,7 +341,7 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     for (int b = 0; b < kSrvGens && ok; ++b)
         ok = pinned(&s->h_srcs2[b], 2 * (size_t)max_slots) && pinned(&s->h_desc2[b], max_slots) &&
              pinned(&s->h_chunks2[b], (size_t)max_place_chunks(s->V, s->E, s->S)) &&
-             pinned(&s->h_off_b2[b], max_slots + 1);
+             pinned(&s->h_off_b2[b], max_slots + 1) && pinned(&s->h_adm2[b], adm_bytes(s->V, s->E, s->S));
     if (!ok) { fastsv_server_destroy(s); return FASTSV_ENOMEM; }
     // copy stream at the default priority, and its events
     bool evs_ok = hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) == hipSuccess &&
@@ -370,7 +385,8 @@ void fastsv_server_destroy(fastsv_server *s) {
     for (void *h : {(void *)s->h_flags, (void *)s->h_out, (void *)s->h_edges, (void *)s->h_step})
         if (h) (void)hipHostFree(h);
     for (int g = 0; g < kSrvGens; ++g) {
-        for (void *h : {(void *)s->h_desc2[g], (void *)s->h_chunks2[g], (void *)s->h_off_b2[g], (void *)s->h_srcs2[g]})
+        for (void *h : {(void *)s->h_desc2[g], (void *)s->h_chunks2[g], (void *)s->h_off_b2[g], (void *)s->h_srcs2[g],
+                        (void *)s->h_adm2[g]})
             if (h) (void)hipHostFree(h);
         if (s->ev_placed[g]) (void)hipEventDestroy(s->ev_placed[g]);
         if (s->ev_dma[g]) (void)hipEventDestroy(s->ev_dma[g]);
@@ -575,13 +591,22 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     }
     if (nnew > 0) {
         h_off_b[nnew] = new_rows;
-        SRV_TRY(hipMemcpyAsync(s->desc, h_desc, sizeof(SrvNew) * nnew, hipMemcpyHostToDevice, cs));
-        SRV_TRY(hipMemcpyAsync(s->srcs, h_srcs, sizeof(void *) * 2 * nnew, hipMemcpyHostToDevice, cs));
-        SRV_TRY(hipMemcpyAsync(s->chunks, h_chunks, sizeof(PlaceChunk) * nchunks, hipMemcpyHostToDevice, cs));
-        SRV_TRY(hipMemcpyAsync(s->off_b, h_off_b, sizeof(int) * (nnew + 1), hipMemcpyHostToDevice, cs));
-        launch_srv_place(cs, nchunks, s->chunks, s->desc, s->srcs, s->rp, s->col, s->F[0], s->F[1], s->G, s->M,
+        // the admission's descriptors, source pointers, row offsets and
+        // placement chunks, packed and copied at once
+        const AdmLayout A = adm_layout(nnew, nchunks);
+        char *ha = s->h_adm2[gen];
+        memcpy(ha + A.desc, h_desc, sizeof(SrvNew) * nnew);
+        memcpy(ha + A.srcs, h_srcs, sizeof(void *) * 2 * nnew);
+        memcpy(ha + A.off_b, h_off_b, sizeof(int) * (nnew + 1));
+        memcpy(ha + A.chunks, h_chunks, sizeof(PlaceChunk) * nchunks);
+        SRV_TRY(hipMemcpyAsync(s->adm, ha, A.total, hipMemcpyHostToDevice, cs));
+        const SrvNew *d_desc = reinterpret_cast<const SrvNew *>(s->adm + A.desc);
+        const int *const *d_srcs = reinterpret_cast<const int *const *>(s->adm + A.srcs);
+        const int *d_off_b = reinterpret_cast<const int *>(s->adm + A.off_b);
+        const PlaceChunk *d_chunks = reinterpret_cast<const PlaceChunk *>(s->adm + A.chunks);
+        launch_srv_place(cs, nchunks, d_chunks, d_desc, d_srcs, s->rp, s->col, s->F[0], s->F[1], s->G, s->M,
                          s->vbase, s->lastk);
-        launch_srv_tiles(cs, nnew, new_rows, s->desc, s->off_b, s->rp, s->tiles);
+        launch_srv_tiles(cs, nnew, new_rows, d_desc, d_off_b, s->rp, s->tiles);
         SRV_TRY(hipGetLastError());
         SRV_TRY(hipEventRecord(s->ev_placed[gen], cs));
         SRV_TRY(hipEventRecord(s->ev_dma[gen], s->ds));
@@ -604,7 +629,7 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     int *h_blk = reinterpret_cast<int *>(s->h_step + SL.blk_off);
     SrvNew *h_dense = reinterpret_cast<SrvNew *>(s->h_step + SL.dense);
     int *h_off_dense = reinterpret_cast<int *>(s->h_step + SL.off_dense);
-    int nrun = 0, ns = 0, vhigh = 0, ndense = 0, dense_tiles = 0, blocks = 0;
+    int nrun = 0, ns = 0, vlow = INT32_MAX, vhigh = 0, ndense = 0, dense_tiles = 0, blocks = 0;
     int64_t fedge_all = 0;
     bool any_sparse = false;
     s->run_slot.clear();
@@ -620,6 +645,7 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         ++nrun;
         if (sl.cancel) continue;
         ++ns;
+        vlow = std::min(vlow, sl.vb);
         vhigh = std::max(vhigh, sl.vb + sl.n + 1);
         fedge_all += sl.fedge;
         const bool dense = sl.admit_step == step || (double)sl.fedge > (double)s->opts.frontier_tau * (double)sl.nnz;
@@ -645,12 +671,11 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         const int *d_off_dense = reinterpret_cast<const int *>(s->stepbuf + SL.off_dense);
         int *F = s->F[(step + 1) & 1], *Fn = s->F[step & 1];
         if (ns > 0) {
-            launch_zero_iter(st, ic);
+            // (a step with a settle pass cleared these for this one)
+            if (!s->next_ic_clean) launch_zero_iter(st, ic);
             if (ndense > 0) {
-                launch_srv_dense_tiles(st, ndense, dense_tiles, d_dense, d_off_dense, s->tiles, s->step_tiles,
-                                       s->gmode, step);
-                launch_dense(st, kDenseBaseGather, s->step_tiles, dense_tiles, s->rp, s->col, s->vbase, F, Fn, s->G,
-                             s->M);
+                launch_srv_dense(st, ndense, dense_tiles, d_dense, d_off_dense, s->tiles, s->gmode, step, s->rp,
+                                 s->col, s->vbase, F, Fn, s->G, s->M);
                 s->st.dense_steps++;
             }
             if (any_sparse) {
@@ -662,13 +687,16 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
                                   s->gmode, step);
                 s->st.sparse_steps++;
             }
+            // the running graphs lie in [vlow, vhigh); below and above it the
+            // pool holds only free or staged (unchanging) vertices
             launch_grandparent(st, vhigh, Fn, s->G, F, s->rp, s->frontier, s->eoff, ic, 1, s->lastk, step, s->vbase,
-                               s->gedge);
+                               s->gedge, nullptr, vlow);
         }
         launch_srv_settle(st, nrun, blocks, d_run, d_blk, step, s->lastk, s->gedge, s->d_flags, s->d_edges, s->d_out,
-                          s->F[0], s->F[1], s->G, s->M, s->vbase);
+                          s->F[0], s->F[1], s->G, s->M, s->vbase, &s->ctr->it[(step + 1) & 1]);
         SRV_TRY(hipGetLastError());
     }
+    s->next_ic_clean = nrun > 0;
     SRV_TRY(hipStreamSynchronize(st));
     int left = 0;  // graphs that left in this step
     for (int j = 0; j < nrun; ++j) {

@@ -77,6 +77,9 @@ class Server:
             raise B.FastSVError(st, "fastsv_server_create")
         self.h = h
         self.pending = {}  # ticket -> (labels, iters, rp, col) kept alive until done
+        self._done = (ctypes.c_uint64 * 4096)()  # poll buffer, reused
+        self._nd = ctypes.c_int32()
+        self._r, self._q = ctypes.c_int32(), ctypes.c_int32()
 
     def submit(self, row_ptr: np.ndarray, col: np.ndarray, mapped: bool = False) -> int:
         """mapped=True: row_ptr and col are page-locked arrays from pin_graphs
@@ -130,7 +133,7 @@ class Server:
         return tl
 
     def step(self):
-        r, q = ctypes.c_int32(), ctypes.c_int32()
+        r, q = self._r, self._q
         st = self.lib.fastsv_server_step(self.h, ctypes.byref(r), ctypes.byref(q))
         if st != B.FASTSV_OK:
             raise B.FastSVError(st, "fastsv_server_step")
@@ -146,14 +149,15 @@ class Server:
         return st
 
     def poll(self):
-        cap = 4096
-        buf = (ctypes.c_uint64 * cap)()
+        buf, k = self._done, self._nd
+        cap = len(buf)
         out = []
         while True:
-            k = ctypes.c_int32()
             st = self.lib.fastsv_server_poll(self.h, buf, cap, ctypes.byref(k))
             if st != B.FASTSV_OK:
                 raise B.FastSVError(st, "fastsv_server_poll")
+            if k.value == 0:
+                return out
             for t in buf[:k.value]:
                 p = self.pending.pop(t)
                 if len(p) == 2:  # from submit_many: (shared record, index)

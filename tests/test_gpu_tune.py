@@ -16,7 +16,7 @@ def test_every_candidate_keeps_the_trajectory(gpu_ok):
     import paper_1910_05971_amd as fs
     for g in (gg.rmat(16, 16, seed=91), gg.grid(300, 300, 0.55, seed=92), gg.er(50000, 150000, seed=93)):
         want = O.uf_labels(g.n, g.row_ptr, g.col)
-        ref = O.fastsv_alg2(g.n, g.row_ptr, g.col)
+        ref = O.fastsv_alg2(g.n, g.row_ptr, g.col, trace_cap=256, record_f=False)
         rp, col = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
         for c in tune.csr_candidates(g.n, g.nnz, all_bins=True):
             print(f"[gpu] tune candidate {g.name} {c}", flush=True)
