@@ -213,14 +213,17 @@ def bench_solve(args, fs, torch, np):
     its = min(per_iter.iterations, 64) if per_iter else 0
     dense_ks = [k for k in range(1, its) if not per_iter.sparse[k]]
     # atomics per launch, from the traced solve (its iterates are the timed ones')
-    a_dense = sum(atomics[k] for k in dense_ks) / len(dense_ks) if dense_ks else 0.0
     a_first = atomics[0] if atomics else 0
     if gather_n:
-        # one dense SpMV step (one launch): row_ptr, col, the G[col] gathers, then G, F, M per row,
-        # and each atomic of the hooks as a read-modify-write
-        kernels.append(roofline_record(f"k_bin_pull<{span}>" if binned else "k_tile_reduce<kGather>",
-                                       "one dense SpMV step", 4 * (n + 1) + 8 * nnz + 12 * n + 8 * a_dense,
-                                       gather_ms, gather_n, args.steps, src_hash, traffic_db))
+        # one dense SpMV step (one launch), as the library counts it for the
+        # traced solve: row_ptr, col, the G[col] gathers, then G, F, M per
+        # row, and each atomic of the hooks as a read-modify-write
+        hook_bytes = tr.alg_hook_list()
+        per_launch = sum(hook_bytes[k] for k in dense_ks) / len(dense_ks)
+        rec = roofline_record(f"k_bin_pull<{span}>" if binned else "k_tile_reduce<kGather>",
+                              "one dense SpMV step", per_launch, gather_ms, gather_n, args.steps, src_hash,
+                              traffic_db)
+        kernels.append(rec)
     if fused and first_ms > 0:
         # the layout fill that also performs the first iteration: col and row_ptr
         # read, one 4-byte record per entry written (the markers, at most 256 per
@@ -259,6 +262,7 @@ def bench_solve(args, fs, torch, np):
             {"k": k + 1, "changed": per_iter.changed[k], "changed_frac": per_iter.changed[k] / n,
              "pass": "sparse" if per_iter.sparse[k] else ("fill+first" if k == 0 and fused else "dense"),
              "pushed": per_iter.pushed[k], "atomics": atomics[k] if k < len(atomics) else None,
+             "alg_hook_bytes": tr.alg_hook[k],
              "ms_hook": per_iter.ms_hook[k], "ms_gp": per_iter.ms_gp[k]} for k in range(its)],
     }
     cpu = None

@@ -147,6 +147,9 @@ typedef struct {
     int32_t sparse[FASTSV_TRACE_ITERS];   /* 1 if iteration k used the sparse push */
     int64_t pushed[FASTSV_TRACE_ITERS];   /* edge slots pushed in iteration k (sparse iterations; 0 if dense) */
     int64_t atomics[FASTSV_TRACE_ITERS];  /* global atomics of iteration k's hooking (opts.trace), else -1 */
+    int64_t alg_hook[FASTSV_TRACE_ITERS]; /* algorithmic bytes of iteration k's hooking pass (the
+                                             SpMV and the hooks, as in alg_bytes; without the
+                                             grandparent pass and the layout build) */
     float ms_hook[FASTSV_TRACE_ITERS];    /* hooking kernel time of iteration k (opts.timing) */
     float ms_gp[FASTSV_TRACE_ITERS];      /* grandparent/termination kernel time, with the frontier list
                                              build when one follows (opts.timing) */

@@ -56,6 +56,7 @@ class Stats(ctypes.Structure):
                 ("atomics_issued", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("changed", ctypes.c_int64 * TRACE_ITERS), ("sparse", ctypes.c_int32 * TRACE_ITERS),
                 ("pushed", ctypes.c_int64 * TRACE_ITERS), ("atomics", ctypes.c_int64 * TRACE_ITERS),
+                ("alg_hook", ctypes.c_int64 * TRACE_ITERS),
                 ("ms_hook", ctypes.c_float * TRACE_ITERS), ("ms_gp", ctypes.c_float * TRACE_ITERS)]
 
     def changed_list(self):
@@ -66,6 +67,9 @@ class Stats(ctypes.Structure):
 
     def pushed_list(self):
         return [int(self.pushed[i]) for i in range(min(self.iterations, TRACE_ITERS))]
+
+    def alg_hook_list(self):
+        return [int(self.alg_hook[i]) for i in range(min(self.iterations, TRACE_ITERS))]
 
     def atomics_list(self):
         return [int(self.atomics[i]) for i in range(min(self.iterations, TRACE_ITERS))]

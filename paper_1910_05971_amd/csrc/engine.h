@@ -213,10 +213,9 @@ void launch_srv_settle(hipStream_t s, int nrun, int blocks, const SrvRun *run, c
 void launch_srv_dense(hipStream_t s, int ndense, int total_tiles, const SrvNew *desc, const int *tile_off,
                       const Tile *pool_tiles, int *mark, int step, const int *rp, const int *col, const int *vbase,
                       const int *F, int *Fn, const int *G, int *M);
+// placement of admitted graphs, with the tiles of their dense first iteration
 void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
                       const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
-                      int *lastk);
-void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,
-                      Tile *tiles);
+                      int *lastk, Tile *tiles);
 
 }  // namespace fsv

@@ -319,17 +319,12 @@ void launch_srv_dense(hipStream_t s, int ndense, int total_tiles, const SrvNew *
 
 void launch_srv_place(hipStream_t s, int nchunks, const PlaceChunk *chunks, const SrvNew *desc,
                       const int *const *srcs, int *rp, int *col, int *F0, int *F1, int *G, int *M, int *vbase,
-                      int *lastk) {
+                      int *lastk, Tile *tiles) {
     if (nchunks <= 0) return;
     hipLaunchKernelGGL(k_srv_place, dim3(nchunks), dim3(256), 0, s, chunks, desc, srcs, rp, col, F0, F1, G, M, vbase,
-                       lastk);
+                       lastk, tiles);
 }
 
-void launch_srv_tiles(hipStream_t s, int nnew, int rows, const SrvNew *desc, const int *row_off, const int *rp,
-                      Tile *tiles) {
-    if (nnew <= 0 || rows <= 0) return;
-    hipLaunchKernelGGL(k_srv_tiles, dim3(grid_for(rows, 256, 8192)), dim3(256), 0, s, nnew, desc, row_off, rp, tiles);
-}
 
 }  // namespace fsv
 
@@ -649,6 +644,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                             (opts.frontier_tau >= 1.0f || (double)prev_edges < tau_edges);
         const int ti = it - 1;
         const bool timed = opts.timing && ti < FASTSV_TRACE_ITERS;
+        const int64_t alg_before = alg;  // the iteration's bytes start here
         // iteration 1 gathers too when it starts from a given f
         const bool gathers = it > 1 || warm;
         if (!sparse && gathers && bin_state == 0) {
@@ -704,6 +700,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             alg += 4 * ((int64_t)n + 1) + (gathers ? 8 : 4) * nnz + 12 * (int64_t)n + (base ? 4 * (int64_t)n : 0);
         }
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
+        int64_t alg_hook = alg - alg_before;  // the hooking pass's bytes (completed below)
         const bool want_frontier = opts.frontier_tau > 0.0f;
         launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 2 : 0, P.lastk, it,
                            P.vbase, nullptr, w.fmask);
@@ -713,6 +710,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
         const int64_t atomics = opts.trace ? (int64_t)hc->atomics : -1;
+        if (atomics > 0) alg_hook += 8 * atomics;
         // read Fn[u], gather Fn[Fn[u]], read G[u], write G[u] and the next seed
         // (with the frontier wanted: a mask bit per vertex); each counted
         // atomic is a read-modify-write of 4 bytes
@@ -745,6 +743,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             stats->sparse[ti] = sparse ? 1 : 0;
             stats->pushed[ti] = sparse ? prev_edges : 0;
             stats->atomics[ti] = atomics;
+            stats->alg_hook[ti] = alg_hook;
             if (timed) {
                 float a = 0, b = 0;
                 HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));

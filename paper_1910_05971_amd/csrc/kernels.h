@@ -1177,18 +1177,35 @@ __global__ __launch_bounds__(256) void k_srv_place(const PlaceChunk *__restrict_
                                                    const int *const *__restrict__ srcs, int *__restrict__ rp,
                                                    int *__restrict__ col, int *__restrict__ F0, int *__restrict__ F1,
                                                    int *__restrict__ G, int *__restrict__ M, int *__restrict__ vbase,
-                                                   int *__restrict__ lastk) {
+                                                   int *__restrict__ lastk, Tile *__restrict__ tiles) {
     const PlaceChunk c = chunks[blockIdx.x];
     const SrvNew d = desc[c.k];
     const int end = c.start + c.count;
     if (c.part == 0) {
         const int *__restrict__ srp = srcs[2 * c.k];
+        Tile *tb = tiles + d.tile_base;
         for (int i = c.start + threadIdx.x; i < end; i += blockDim.x) {
             const int u = d.vb + i;
-            rp[u] = srp[i] + d.eb;
+            const int s0 = srp[i];
+            rp[u] = s0 + d.eb;
             F0[u] = u; F1[u] = u; G[u] = u; M[u] = u;
             vbase[u] = d.vb;
             lastk[u] = 0;
+            if (i == d.n) continue;
+            // the graph's tiles for its dense first iteration: the row holding
+            // a tile's first entry writes its range and r_lo, the row holding
+            // its last entry r_hi (each tile has one writer of each)
+            const int e0 = srp[i + 1];
+            for (int t = s0 / kTileEntries; s0 < e0 && t <= (e0 - 1) / kTileEntries; ++t) {
+                const int t0 = t * kTileEntries;
+                const int last = min(t0 + kTileEntries, d.nnz) - 1;
+                if (t0 >= s0 && t0 < e0) {
+                    tb[t].e0 = d.eb + t0;
+                    tb[t].e1 = d.eb + last + 1;
+                    tb[t].r_lo = u;
+                }
+                if (last >= s0 && last < e0) tb[t].r_hi = u;
+            }
         }
         return;
     }
@@ -1210,29 +1227,5 @@ __global__ __launch_bounds__(256) void k_srv_place(const PlaceChunk *__restrict_
     }
 }
 
-// Tiles of the newly admitted graphs for their dense first iteration; rows
-// numbered across the batch (row_off = exclusive prefix of n).
-__global__ void k_srv_tiles(int nnew, const SrvNew *__restrict__ desc, const int *__restrict__ row_off,
-                            const int *__restrict__ rp, Tile *__restrict__ tiles) {
-    const int total = row_off[nnew];
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += gridDim.x * blockDim.x) {
-        const int k = find_owner(row_off, nnew, x);
-        const SrvNew d = desc[k];
-        const int r = d.vb + (x - row_off[k]);
-        const int s = rp[r] - d.eb, e = rp[r + 1] - d.eb;
-        if (s >= e) continue;
-        Tile *tb = tiles + d.tile_base;
-        for (int t = s / kTileEntries; t <= (e - 1) / kTileEntries; ++t) {
-            int t0 = t * kTileEntries;
-            int last = min(t0 + kTileEntries, d.nnz) - 1;
-            if (t0 >= s && t0 < e) {
-                tb[t].e0 = d.eb + t0;
-                tb[t].e1 = d.eb + last + 1;
-                tb[t].r_lo = r;
-            }
-            if (last >= s && last < e) tb[t].r_hi = r;
-        }
-    }
-}
 
 }  // namespace fsv

@@ -133,9 +133,9 @@ inline int64_t max_place_chunks(int64_t V, int64_t E, int64_t S) {
 }
 
 // One admission's arrays, packed for a single host-to-device copy (16-byte
-// aligned): descriptors, source pointers, row offsets, placement chunks.
+// aligned): descriptors, source pointers, placement chunks.
 struct AdmLayout {
-    size_t desc, srcs, off_b, chunks, total;
+    size_t desc, srcs, chunks, total;
 };
 
 inline AdmLayout adm_layout(int64_t nnew, int64_t nchunks) {
@@ -143,8 +143,7 @@ inline AdmLayout adm_layout(int64_t nnew, int64_t nchunks) {
     AdmLayout A;
     A.desc = 0;
     A.srcs = al(A.desc + sizeof(SrvNew) * (size_t)nnew);
-    A.off_b = al(A.srcs + sizeof(void *) * 2 * (size_t)nnew);
-    A.chunks = al(A.off_b + sizeof(int) * (size_t)(nnew + 1));
+    A.chunks = al(A.srcs + sizeof(void *) * 2 * (size_t)nnew);
     A.total = A.chunks + sizeof(PlaceChunk) * (size_t)nchunks;
     return A;
 }
@@ -197,7 +196,7 @@ struct fastsv_server {
     int64_t admit_bytes = 0;  // graph bytes admitted per step once one graph is in
     char *pool = nullptr;
     PoolLayout L{};
-    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *stage, *off_b, *gmode, *gedge;
+    int *rp, *col, *F[2], *G, *M, *vbase, *lastk, *frontier, *eoff, *stage, *gmode, *gedge;
     PlaceChunk *chunks;
     SrvNew *desc;
     const int **srcs;
@@ -213,13 +212,14 @@ struct fastsv_server {
     char *h_step = nullptr;  // the step descriptor
     // admission buffers, rotating over kSrvGens generations, since the copy
     // streams may still read earlier steps' while the host prepares the next
-    int *h_off_b2[kSrvGens] = {};
     PlaceChunk *h_chunks2[kSrvGens] = {};
     SrvNew *h_desc2[kSrvGens] = {};
     const int **h_srcs2[kSrvGens] = {};
     char *h_adm2[kSrvGens] = {};  // the four arrays above packed for one copy
     char *adm = nullptr;          // its device copy
     bool next_ic_clean = true;    // the next step's counters were cleared by a settle pass
+    std::vector<char> step_last;  // the step descriptor bytes the device holds
+    size_t step_held = 0;
     RangeAlloc va, ea, ta;
     // ranges of graphs that left in the current step: allocatable from the
     // next step on, after their reset (compute stream) has completed, so that
@@ -341,7 +341,7 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     for (int b = 0; b < kSrvGens && ok; ++b)
         ok = pinned(&s->h_srcs2[b], 2 * (size_t)max_slots) && pinned(&s->h_desc2[b], max_slots) &&
              pinned(&s->h_chunks2[b], (size_t)max_place_chunks(s->V, s->E, s->S)) &&
-             pinned(&s->h_off_b2[b], max_slots + 1) && pinned(&s->h_adm2[b], adm_bytes(s->V, s->E, s->S));
+             pinned(&s->h_adm2[b], adm_bytes(s->V, s->E, s->S));
     if (!ok) { fastsv_server_destroy(s); return FASTSV_ENOMEM; }
     // copy stream at the default priority, and its events
     bool evs_ok = hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) == hipSuccess &&
@@ -385,8 +385,7 @@ void fastsv_server_destroy(fastsv_server *s) {
     for (void *h : {(void *)s->h_flags, (void *)s->h_out, (void *)s->h_edges, (void *)s->h_step})
         if (h) (void)hipHostFree(h);
     for (int g = 0; g < kSrvGens; ++g) {
-        for (void *h : {(void *)s->h_desc2[g], (void *)s->h_chunks2[g], (void *)s->h_off_b2[g], (void *)s->h_srcs2[g],
-                        (void *)s->h_adm2[g]})
+        for (void *h : {(void *)s->h_desc2[g], (void *)s->h_chunks2[g], (void *)s->h_srcs2[g], (void *)s->h_adm2[g]})
             if (h) (void)hipHostFree(h);
         if (s->ev_placed[g]) (void)hipEventDestroy(s->ev_placed[g]);
         if (s->ev_dma[g]) (void)hipEventDestroy(s->ev_dma[g]);
@@ -524,9 +523,8 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     //    stream work (which reads them) has completed.
     SrvNew *h_desc = s->h_desc2[gen];
     const int **h_srcs = s->h_srcs2[gen];
-    int *h_off_b = s->h_off_b2[gen];
     PlaceChunk *h_chunks = s->h_chunks2[gen];
-    int nnew = 0, new_rows = 0, nchunks = 0;
+    int nnew = 0, nchunks = 0;
     int64_t staged = 0;
     std::vector<int> admitted;
     int64_t admit_bytes = 0;
@@ -559,11 +557,13 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         sl.iters_out = r.iters_out;
         admitted.push_back(k);
         SrvNew d{(int)vb, (int)eb, r.n, (int)r.nnz, (int)staged, (int)(staged + r.n + 1), (int)tb, 0};
-        // row pointers: read in place when page-locked, else staged by DMA;
-        // column ids: by DMA straight into the pool when pageable or large,
-        // else read in place by the placement kernel
+        // row pointers: read in place when page-locked and small, else staged
+        // by DMA; column ids: by DMA straight into the pool when pageable or
+        // large, else read in place by the placement kernel
         const bool col_dma = r.nnz > 0 && (!r.dcol || r.nnz >= kSrvDmaMinEntries);
-        if (r.drp) {
+        // (row pointers of large graphs go by DMA too: the placement kernel
+        // then reads them from device memory)
+        if (r.drp && (int64_t)r.n + 1 < kSrvDmaMinEntries) {
             h_srcs[2 * nnew] = r.drp;
         } else {
             SRV_TRY(hipMemcpyAsync(s->stage + d.s_rp, r.rp, sizeof(int) * (size_t)(r.n + 1), hipMemcpyHostToDevice,
@@ -577,36 +577,30 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         }
         h_srcs[2 * nnew + 1] = col_dma ? nullptr : r.dcol;
         h_desc[nnew] = d;
-        h_off_b[nnew] = new_rows;
         for (int c0 = 0; c0 <= r.n; c0 += kPlaceChunk)
             h_chunks[nchunks++] = PlaceChunk{nnew, 0, c0, std::min(kPlaceChunk, r.n + 1 - c0)};
         if (!col_dma)
             for (int64_t c0 = 0; c0 < r.nnz; c0 += kPlaceChunk)
                 h_chunks[nchunks++] = PlaceChunk{nnew, 1, (int)c0, (int)std::min<int64_t>(kPlaceChunk, r.nnz - c0)};
         admit_bytes += sizeof(int) * ((int64_t)r.n + 1 + r.nnz);
-        new_rows += r.n;
         ++nnew;
         s->queue.pop_front();
         s->st.admitted++;
     }
     if (nnew > 0) {
-        h_off_b[nnew] = new_rows;
-        // the admission's descriptors, source pointers, row offsets and
-        // placement chunks, packed and copied at once
+        // the admission's descriptors, source pointers and placement
+        // chunks, packed and copied at once
         const AdmLayout A = adm_layout(nnew, nchunks);
         char *ha = s->h_adm2[gen];
         memcpy(ha + A.desc, h_desc, sizeof(SrvNew) * nnew);
         memcpy(ha + A.srcs, h_srcs, sizeof(void *) * 2 * nnew);
-        memcpy(ha + A.off_b, h_off_b, sizeof(int) * (nnew + 1));
         memcpy(ha + A.chunks, h_chunks, sizeof(PlaceChunk) * nchunks);
         SRV_TRY(hipMemcpyAsync(s->adm, ha, A.total, hipMemcpyHostToDevice, cs));
         const SrvNew *d_desc = reinterpret_cast<const SrvNew *>(s->adm + A.desc);
         const int *const *d_srcs = reinterpret_cast<const int *const *>(s->adm + A.srcs);
-        const int *d_off_b = reinterpret_cast<const int *>(s->adm + A.off_b);
         const PlaceChunk *d_chunks = reinterpret_cast<const PlaceChunk *>(s->adm + A.chunks);
         launch_srv_place(cs, nchunks, d_chunks, d_desc, d_srcs, s->rp, s->col, s->F[0], s->F[1], s->G, s->M,
-                         s->vbase, s->lastk);
-        launch_srv_tiles(cs, nnew, new_rows, d_desc, d_off_b, s->rp, s->tiles);
+                         s->vbase, s->lastk, s->tiles);
         SRV_TRY(hipGetLastError());
         SRV_TRY(hipEventRecord(s->ev_placed[gen], cs));
         SRV_TRY(hipEventRecord(s->ev_dma[gen], s->ds));
@@ -661,10 +655,17 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     if (nrun > 0) {
         h_blk[nrun] = blocks;
         h_off_dense[ndense] = dense_tiles;
-        // one copy of the used part of the descriptor
+        // one copy of the used part of the descriptor, skipped when the
+        // device already holds the same bytes (the running set and its dense
+        // choices often stay the same from one step to the next)
         const size_t bytes = ndense > 0 ? SL.off_dense + sizeof(int) * (size_t)(ndense + 1)
                                         : SL.blk_off + sizeof(int) * (size_t)(nrun + 1);
-        SRV_TRY(hipMemcpyAsync(s->stepbuf, s->h_step, bytes, hipMemcpyHostToDevice, st));
+        const bool same = bytes <= s->step_held && !memcmp(s->step_last.data(), s->h_step, bytes);
+        if (!same) {
+            SRV_TRY(hipMemcpyAsync(s->stepbuf, s->h_step, bytes, hipMemcpyHostToDevice, st));
+            s->step_last.assign(s->h_step, s->h_step + bytes);
+            s->step_held = bytes;
+        }
         const SrvRun *d_run = reinterpret_cast<const SrvRun *>(s->stepbuf + SL.run);
         const int *d_blk = reinterpret_cast<const int *>(s->stepbuf + SL.blk_off);
         const SrvNew *d_dense = reinterpret_cast<const SrvNew *>(s->stepbuf + SL.dense);
