@@ -110,7 +110,7 @@ def roofline_record(kernel, unit, alg_bytes, total_ms, launches, solves, src_has
     only while the kernel sources are those the counters were taken with."""
     avg_ms = total_ms / max(launches, 1)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    traffic, note = None, "no counter record"
+    traffic, by_req, l2_hit, note = None, None, None, "no counter record"
     rec = traffic_db.get(kernel)
     if "_error" in traffic_db:
         note = f"unreadable counter record: {traffic_db['_error']}"
@@ -118,9 +118,13 @@ def roofline_record(kernel, unit, alg_bytes, total_ms, launches, solves, src_has
         if rec.get("kernel_source_sha256_16") != src_hash:
             note = "kernel source changed since the counters were taken"
         else:
+            # FETCH_SIZE + WRITE_SIZE, copy-scaled; beside it the same bytes
+            # from the read and write request counts by request size
             traffic, note = rec.get("hbm_bytes_per_launch"), rec.get("source")
+            by_req, l2_hit = rec.get("request_bytes_per_launch"), rec.get("l2_hit")
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": note, "kernel": kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_by_request_size": by_req,
+            "l2_hit": l2_hit, "traffic_note": note, "kernel": kernel,
             "unit_of_work": unit, "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": avg_ms,
             "launches_timed": launches, "ms_per_solve": total_ms / max(solves, 1),
             "kernel_source_sha256_16": src_hash}

@@ -228,6 +228,9 @@ struct fastsv_server {
     std::deque<Request> queue;
     std::vector<Slot> slots;
     std::vector<int> free_slots;  // stack of free slot indices
+    // the slots in use (staged or running), in admission order: a step
+    // visits these only, however many slots the server was created with
+    std::vector<int> active;
     std::vector<int> run_slot;    // slot of each entry of the step's run list
     std::deque<uint64_t> done;
     int step = 0;
@@ -357,6 +360,7 @@ int fastsv_server_create(fastsv_ctx *ctx, int32_t max_vertices, int64_t max_entr
     s->ea.reset(s->E);
     s->ta.reset(s->T);
     s->slots.assign(max_slots, Slot{});
+    s->active.reserve(max_slots);
     for (int i = max_slots - 1; i >= 0; --i) s->free_slots.push_back(i);
     // neutral state everywhere: every pool vertex its own root, empty rows
     launch_fill(stream, (int)(s->V + 1), s->rp, 0);
@@ -502,7 +506,8 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     int gen_state[kSrvGens];
     for (int g = 0; g < kSrvGens; ++g) gen_state[g] = -2;  // not queried yet
     int nrunning = 0;
-    for (Slot &sl : s->slots) {
+    for (const int i : s->active) {
+        Slot &sl = s->slots[i];
         if (sl.state == kStaged) {
             int &gs = gen_state[sl.gen];
             if (gs == -2) gs = generation_done(s, sl.gen);
@@ -542,6 +547,7 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         const int64_t tb = s->ta.alloc(ntiles);
         if (tb < 0) { s->va.release(vb, r.n + 1); s->ea.release(eb, r.nnz); break; }
         s->free_slots.pop_back();
+        s->active.push_back(k);
         Slot &sl = s->slots[k];
         sl = Slot{};
         sl.state = kStaged;
@@ -627,7 +633,7 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
     int64_t fedge_all = 0;
     bool any_sparse = false;
     s->run_slot.clear();
-    for (int i = 0; i < s->S; ++i) {
+    for (const int i : s->active) {
         Slot &sl = s->slots[i];
         // a cancelled graph is settled once its admission copies are complete
         const bool staged_cancel = sl.state == kStaged && sl.cancel && gen_state[sl.gen] == 1;
@@ -723,13 +729,12 @@ int fastsv_server_step(fastsv_server *s, int32_t *n_resident, int32_t *n_queued)
         s->free_slots.push_back(i);
         ++left;
     }
-    (void)left;
+    if (left > 0)
+        s->active.erase(std::remove_if(s->active.begin(), s->active.end(),
+                                       [s](int i) { return s->slots[i].state == kFree; }),
+                        s->active.end());
     s->st.steps++;
-    if (n_resident) {
-        int r = 0;  // admitted and not left: running or staged
-        for (const Slot &sl : s->slots) r += sl.state != kFree;
-        *n_resident = r;
-    }
+    if (n_resident) *n_resident = (int32_t)s->active.size();  // admitted and not left: running or staged
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     return FASTSV_OK;
 }
@@ -742,8 +747,9 @@ int fastsv_server_cancel(fastsv_server *s, uint64_t ticket) {
             s->st.cancelled++;
             return FASTSV_OK;
         }
-    for (Slot &sl : s->slots) {
-        if (sl.state == kFree || sl.ticket != ticket) continue;
+    for (const int i : s->active) {
+        Slot &sl = s->slots[i];
+        if (sl.ticket != ticket) continue;
         if (sl.cancel) return FASTSV_OK;
         if (sl.state == kStaged) {
             const int g = generation_done(s, sl.gen);

@@ -211,7 +211,10 @@ def run_open_loop(server: Server, graphs, arrivals, on_done=None, idle_sleep=0.0
                 ticket_of[t] = i
         outstanding += len(arrived)
         if outstanding:
-            server.step()
+            resident, queued = server.step()
+            # poll only when some request has left the server
+            if resident + queued >= outstanding:
+                continue
             for t, lab, its in server.poll():
                 i = ticket_of.pop(t)
                 lat[i] = time.perf_counter() - t0 - arrivals[i]
