@@ -113,9 +113,9 @@ typedef struct {
                                iterate f_k of any k is the result of a call with max_iters = k
                                (FASTSV_ENOTCONVERGED), and the statistics below record the
                                per-iteration figures. */
-    int32_t bin_span;       /* records per lane and step of the binned dense pass: 16 or 32; 0 =
-                               automatic (32 for bins of at least 2^18 records, else 16).  Same
-                               iterates either way. */
+    int32_t bin_span;       /* records per lane and step of the binned dense pass: 8, 16 or 32;
+                               0 = automatic (32 for bins of at least 2^18 records, 16 for at
+                               least 2^17, else 8).  Same iterates either way. */
     int32_t admit_mb;       /* serving only: megabytes of graph data a server step admits once one
                                graph is in (1..4096; 0 = 128) */
 } fastsv_opts;
@@ -133,7 +133,7 @@ typedef struct {
     int32_t bin_fused_first;       /* 1 if the layout's fill pass also performed the first
                                       iteration (that pass is then ms_hook[0]) */
     int32_t bin_span;              /* records per lane and step of the binned dense pass that
-                                      ran (16, or 32 for bins of at least 2^18 records; 0 if none) */
+                                      ran (8, 16 or 32, as opts.bin_span; 0 if none) */
     float ms_bin_prepare;          /* time to build the binned layout; with bin_fused_first only
                                       its count and scan before the fill (opts.timing) */
     int64_t frontier_edges;        /* sum over sparse iterations of the pushed edge slots */

@@ -87,9 +87,15 @@ constexpr int kBinShiftMax = 15;        // largest power-of-two bin width that m
 constexpr int kBinShiftMin = 8;
 constexpr int kBinRowsMax = 40960;      // widest bin: a 160 KB LDS window in the dense pass
 constexpr int kNumCUs = 256;            // MI355X compute units: one dense-pass workgroup each at a time
-constexpr int kBinSpan = 16;            // entries per lane and step of the binned dense pass
-constexpr int kBinSpanWide = 32;        // the same for bins of at least kBinWideMin records
-constexpr int64_t kBinWideMin = 1 << 18; // (a wide step leaves a longer ragged last step per bin)
+// entries per lane and step of the binned dense pass, by the bin's length in
+// records: a longer step leaves a longer ragged last step per bin, and a
+// shorter one keeps the workgroups of an XCD gathering from a narrower slice
+// of G at a time (bins whose sources spread over all of G: short bins)
+constexpr int kBinSpanNarrow = 8;       // bins of fewer than kBinMidMin records
+constexpr int kBinSpan = 16;            // bins of kBinMidMin to kBinWideMin records
+constexpr int kBinSpanWide = 32;        // bins of at least kBinWideMin records
+constexpr int64_t kBinMidMin = 1 << 17;
+constexpr int64_t kBinWideMin = 1 << 18;
 constexpr int kBinThreads = 256;        // layout count pass
 constexpr int kFillThreads = 512;       // layout fill: one tile per wave and round
 constexpr int64_t kBinMaxCounts = 1 << 27;  // (bin, chunk) counters of the layout build
@@ -117,7 +123,7 @@ constexpr int kBinAutoMinN = 1 << 22;   // automatic mode: graphs with more vert
 // wave of the dense pass starts.
 constexpr int kSrcLoBits = 16;
 constexpr unsigned kBinMarker = 0xFFFFu;
-constexpr int kBinCkShift = 10;
+constexpr int kBinCkShift = 9;
 static_assert(kBinRowsMax < (int)kBinMarker, "a row offset never equals the marker tag");
 
 // A graph entering or leaving the serving pool (see server.hip).

@@ -398,7 +398,8 @@ bool opts_ok(const fastsv_opts &o, int64_t n) {
     if (o.mode == kModeAsync && o.sv_flags != kSvFastSV) return false;
     if (o.bin_shift != 0 && (o.bin_shift < kBinShiftMin || o.bin_shift > kBinShiftMax)) return false;
     if (o.trace != 0 && o.trace != 1) return false;
-    if (o.bin_span != 0 && o.bin_span != kBinSpan && o.bin_span != kBinSpanWide) return false;
+    if (o.bin_span != 0 && o.bin_span != kBinSpanNarrow && o.bin_span != kBinSpan && o.bin_span != kBinSpanWide)
+        return false;
     if (o.admit_mb < 0 || o.admit_mb > 4096) return false;
     return true;
 }
@@ -680,17 +681,24 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                              F, Fn, G, w.M, atom);
             } else if (bin_state == 1) {
                 // wide steps only where bins are long enough that the ragged
-                // last step of each bin is a small share
-                const bool wide = opts.bin_span ? opts.bin_span == kBinSpanWide : L.bin_cap / L.nbins >= kBinWideMin;
-                if (wide)
+                // last step of each bin is a small share, narrow ones where
+                // they are short
+                const int64_t per_bin = L.bin_cap / L.nbins;
+                const int span = opts.bin_span ? opts.bin_span
+                                               : per_bin >= kBinWideMin ? kBinSpanWide
+                                                                        : per_bin >= kBinMidMin ? kBinSpan : kBinSpanNarrow;
+                if (span == kBinSpanWide)
                     hipLaunchKernelGGL(k_bin_pull<kBinSpanWide>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
                                        L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M, atom);
-                else
+                else if (span == kBinSpan)
                     hipLaunchKernelGGL(k_bin_pull<kBinSpan>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
                                        L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M, atom);
+                else
+                    hipLaunchKernelGGL(k_bin_pull<kBinSpanNarrow>, dim3(L.nbins), dim3(1024), 0, stream, n,
+                                       L.bdiv.rows, L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M, atom);
                 if (stats) {
                     stats->binned_iterations++;
-                    stats->bin_span = wide ? kBinSpanWide : kBinSpan;
+                    stats->bin_span = span;
                 }
             } else {
                 launch_dense(stream, base ? kDenseBaseGather : kDenseGather, w.tiles, (int)ntiles, P.rp, P.col,

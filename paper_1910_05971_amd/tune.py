@@ -25,7 +25,7 @@ from . import binding as B
 
 TAUS = (0.01, 0.02, 0.05, 0.1, 0.2)
 # (bin_shift, bin_span): automatic width with each span, and two fixed widths
-BIN_CHOICES = ((0, 0), (0, 16), (0, 32), (14, 0), (15, 0))
+BIN_CHOICES = ((0, 0), (0, 8), (0, 16), (0, 32), (14, 0), (15, 0))
 ADMIT_MB = (32, 64, 128, 256)
 BINNED_MIN_N = 1 << 22  # the automatic layout choice (binned above this many vertices)
 

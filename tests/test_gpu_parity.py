@@ -196,14 +196,14 @@ def test_binned_passes_trajectories(gpu_ok):
 
 def test_binned_span_choice(gpu_ok):
     # bins of at least 2^18 records take the wide dense step (32 records per
-    # lane and step), shorter ones the narrow one (16); both are checked
-    # iterate by iterate
+    # lane and step), bins under 2^17 the narrow one (8), and 16 is chosen
+    # explicitly here; each is checked iterate by iterate
     g = gg.rmat(16, 16, seed=69)
-    for shift, span in ((14, 32), (10, 16)):
-        check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift)
+    for shift, ask, span in ((14, 0, 32), (10, 0, 8), (10, 16, 16)):
+        check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift, bin_span=ask)
         rp, col = to_dev(g)
-        _, st = solve(rp, col, frontier_tau=0.0, binned=True, bin_shift=shift)
-        assert st.binned_iterations > 0 and st.bin_span == span, (shift, st.bin_span)
+        _, st = solve(rp, col, frontier_tau=0.0, binned=True, bin_shift=shift, bin_span=ask)
+        assert st.binned_iterations > 0 and st.bin_span == span, (shift, ask, st.bin_span)
 
 
 def test_binned_automatic_width(gpu_ok):
@@ -214,7 +214,7 @@ def test_binned_automatic_width(gpu_ok):
     rp, col = to_dev(g)
     _, st = solve(rp, col)
     assert st.num_bins == 256 and st.binned_iterations > 0 and st.bin_fused_first == 1
-    assert st.bin_span == 16  # about 117K records per bin
+    assert st.bin_span == 8  # about 117K records per bin
 
 
 def test_binned_source_high_bits(gpu_ok):

@@ -13,7 +13,7 @@ def test_candidates_cover_the_grid():
     assert len(big) == len(tune.TAUS) * len(tune.BIN_CHOICES)
     assert len(tune.csr_candidates(1000, 5000, all_bins=True)) == len(big)
     for c in big:
-        assert c["bin_span"] in (0, 16, 32) and c["bin_shift"] in (0, 14, 15)
+        assert c["bin_span"] in (0, 8, 16, 32) and c["bin_shift"] in (0, 14, 15)
 
 
 def test_size_class():
