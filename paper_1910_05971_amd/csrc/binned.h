@@ -426,11 +426,50 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, in
         }
         __syncthreads();
     }
+    // finish the rows (as finish_row: M update, aggressive and stochastic
+    // hooks) kFinishBatch rows per thread at a time, each stage's loads for
+    // the batch issued together: the rows are independent, and a hook's
+    // pre-check read that sees an older (larger) Fn only costs an atomic
     int na = 0;
-    for (int i = tid; i < rows; i += 1024) {
-        const int m = wmin[i];
-        if (m == INT_MAX) continue;
-        na += finish_row<false>(u0 + i, m, false, F, Fn, G, M);
+    for (int i0 = tid; i0 < rows; i0 += 1024 * kFinishBatch) {
+        int m[kFinishBatch], mu[kFinishBatch], gu[kFinishBatch], fnu[kFinishBatch], fu[kFinishBatch],
+            fnx[kFinishBatch];
+#pragma unroll
+        for (int k = 0; k < kFinishBatch; ++k) {
+            const int i = i0 + k * 1024;
+            m[k] = i < rows ? wmin[i] : INT_MAX;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinishBatch; ++k) {
+            const int u = u0 + i0 + k * 1024;
+            mu[k] = m[k] != INT_MAX ? M[u] : INT_MAX;
+            gu[k] = m[k] != INT_MAX ? G[u] : INT_MAX;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinishBatch; ++k) {
+            const int u = u0 + i0 + k * 1024;
+            if (m[k] < mu[k]) M[u] = m[k];
+            const bool hook = m[k] < gu[k];  // (false for a row without entries)
+            fnu[k] = hook ? Fn[u] : INT_MIN;
+            fu[k] = hook ? F[u] : u;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinishBatch; ++k) {
+            const int u = u0 + i0 + k * 1024;
+            fnx[k] = fu[k] != u ? Fn[fu[k]] : INT_MIN;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinishBatch; ++k) {
+            const int u = u0 + i0 + k * 1024;
+            if (fnu[k] > m[k]) {
+                atomicMin(Fn + u, m[k]);
+                ++na;
+            }
+            if (fu[k] != u && fnx[k] > m[k]) {
+                atomicMin(Fn + fu[k], m[k]);
+                ++na;
+            }
+        }
     }
     wave_add_atomics(atom, na);
 }

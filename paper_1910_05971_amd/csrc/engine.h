@@ -96,6 +96,7 @@ constexpr int kBinSpan = 16;            // bins of kBinMidMin to kBinWideMin rec
 constexpr int kBinSpanWide = 32;        // bins of at least kBinWideMin records
 constexpr int64_t kBinMidMin = 1 << 17;
 constexpr int64_t kBinWideMin = 1 << 18;
+constexpr int kFinishBatch = 8;         // rows per thread whose loads the dense pass's row finish batches
 constexpr int kBinThreads = 256;        // layout count pass
 constexpr int kFillThreads = 512;       // layout fill: one tile per wave and round
 constexpr int64_t kBinMaxCounts = 1 << 27;  // (bin, chunk) counters of the layout build
