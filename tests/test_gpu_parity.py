@@ -227,6 +227,10 @@ def test_binned_source_high_bits(gpu_ok):
     g = gg.er(400_000, 1_200_000, seed=71)
     for shift in (12, 15):
         check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift)
+    # the same with each span of the dense pass asked for (the automatic one
+    # is the narrow span here), so that every span meets markers mid-bin
+    for span in (16, 32):
+        check_graph(g, taus=(0.0,), trajectory=True, binned=True, bin_shift=15, bin_span=span)
     n = 1_000_000
     starts = (0, 70_000, 131_000, 300_000, 655_300, 999_900)
     pairs = []
