@@ -78,6 +78,47 @@ def test_batch_small(gpu_ok):
         _check_batch(b, frontier_tau=tau)
 
 
+def _batch_of(graphs):
+    """A Batch holding the given graphs (local column ids, global row_ptr)."""
+    ns = [g.n for g in graphs]
+    nnzs = [g.col.shape[0] for g in graphs]
+    vtx_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int32)
+    edge_off = np.concatenate([[0], np.cumsum(nnzs)]).astype(np.int32)
+    row_ptr = np.concatenate([g.row_ptr[:-1].astype(np.int64) + edge_off[i] for i, g in enumerate(graphs)] +
+                             [[edge_off[-1]]]).astype(np.int32)
+    col = np.concatenate([g.col for g in graphs]).astype(np.int32)
+    m_eff = np.array([g.m_eff for g in graphs], dtype=np.int64)
+    return gg.Batch(np.array(ns, dtype=np.int32), m_eff, vtx_off, edge_off, row_ptr, col)
+
+
+def test_batch_mixed_sizes(gpu_ok):
+    # graphs from 64 to 100000 vertices in one batch (tiles that cross graphs,
+    # graphs over many tiles), stars whose hub rows span 16 and 98 tiles and a
+    # path (many iterations), each against its solo oracle run; also capped
+    # runs against the solo iterates
+    import paper_1910_05971_amd as fs
+    import oracle_pins as P
+    graphs = []
+    for i, n in enumerate((64, 4096, 4097, 16384, 16385, 65536, 65537, 100_000)):
+        graphs.append(gg.er(n, 3 * n, seed=90 + i))
+    for n in (16_384, 100_000):
+        graphs.append(gg.Graph(f"star{n}", n, *P.csr_from_pairs(n, [(7, v) for v in range(n) if v != 7]), n - 1))
+    n = 3000
+    graphs.append(gg.Graph("path", n, *P.csr_from_pairs(n, [(v, v + 1) for v in range(n - 1)]), n - 1))
+    b = _batch_of(graphs)
+    _say(f"[gpu] batch mixed G={b.num_graphs} n={b.row_ptr.shape[0] - 1} nnz={b.col.shape[0]}")
+    for tau in (0.0, 0.05):
+        _check_batch(b, frontier_tau=tau)
+    vo, eo, rp, col = _batch_to_dev(b)
+    refs = [O.fastsv_alg2(g.n, g.row_ptr, g.col, trace_cap=64) for g in graphs]
+    for k in (2, 3, 5):
+        labels, iters, st, status = fs.cc_batch_csr(vo, eo, rp, col, max_iters=k, frontier_tau=0.0, check=False)
+        lab = labels.cpu().numpy()
+        for g, r in enumerate(refs):
+            v0, v1 = int(b.vtx_off[g]), int(b.vtx_off[g + 1])
+            assert np.array_equal(lab[v0:v1], r.trace[min(k, r.iterations) - 1]), (g, k)
+
+
 def test_batch_matches_solo_trajectory(gpu_ok):
     # capped runs: graph g's labels after k iterations are its solo f_k
     import paper_1910_05971_amd as fs
