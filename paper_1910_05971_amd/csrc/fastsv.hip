@@ -206,6 +206,12 @@ void bin_prepare(const Layout &L, const Workspace &w, int n, const int *rp, cons
 }
 
 // ---- launch wrappers ----
+// The iteration counters to the host's mapped mirror (read after the
+// stream's synchronisation): one small kernel instead of a copy command.
+void launch_publish(hipStream_t s, const IterCounters *src, IterCounters *dst) {
+    hipLaunchKernelGGL(k_publish_counters, dim3(1), dim3(64), 0, s, src, dst);
+}
+
 void launch_init(hipStream_t s, int n, int *F, int *Fn, int *G, int *M, int base) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, F, Fn, G, M, base);
@@ -332,7 +338,8 @@ using namespace fsv;
 
 struct fastsv_ctx {
     int device = 0;
-    Counters *host_ctr = nullptr;  // pinned
+    Counters *host_ctr = nullptr;  // pinned, mapped: the kernels' counters are published here
+    Counters *dev_ctr = nullptr;   // host_ctr as the device addresses it
     void *ws = nullptr;
     size_t ws_size = 0;
     hipEvent_t ev[6] = {};  // iteration phases; [4], [5] bracket the frontier list build
@@ -496,7 +503,7 @@ int solve_variant(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Work
                            early ? 1 : 0);
         HIP_TRY(hipGetLastError());
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
-        HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
+        launch_publish(stream, ic, &ctx->dev_ctr->it[it & 1]);
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
         if (stats) {
@@ -563,7 +570,7 @@ int solve_async(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Worksp
         hipLaunchKernelGGL(k_async_shortcut, dim3(grid_for(n, 256, 65536)), dim3(256), 0, stream, n, f, ic);
         HIP_TRY(hipGetLastError());
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
-        HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
+        launch_publish(stream, ic, &ctx->dev_ctr->it[it & 1]);
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
         if (stats) {
@@ -714,7 +721,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                            P.vbase, nullptr, w.fmask);
         HIP_TRY(hipGetLastError());
         if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
-        HIP_TRY(hipMemcpyAsync(hc, ic, sizeof(IterCounters), hipMemcpyDeviceToHost, stream));
+        launch_publish(stream, ic, &ctx->dev_ctr->it[it & 1]);
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
         const int64_t atomics = opts.trace ? (int64_t)hc->atomics : -1;
@@ -738,8 +745,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             launch_frontier_from_mask(stream, n, w.fmask, P.rp, w.frontier, w.eoff, &w.ctr->fb);
             HIP_TRY(hipGetLastError());
             if (timed) HIP_TRY(hipEventRecord(ctx->ev[5], stream));
-            HIP_TRY(hipMemcpyAsync(&ctx->host_ctr->fb, &w.ctr->fb, sizeof(IterCounters), hipMemcpyDeviceToHost,
-                                   stream));
+            launch_publish(stream, &w.ctr->fb, &ctx->dev_ctr->fb);
             HIP_TRY(hipStreamSynchronize(stream));
             edges = (int64_t)(ctx->host_ctr->fb.packed & 0xffffffffull);
             list_ready = true;
@@ -880,10 +886,14 @@ int fastsv_create(fastsv_ctx **out, int device) {
     fastsv_ctx *c = new (std::nothrow) fastsv_ctx();
     if (!c) return FASTSV_ENOMEM;
     c->device = device;
-    if (hipHostMalloc(reinterpret_cast<void **>(&c->host_ctr), sizeof(Counters), hipHostMallocDefault) !=
-        hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->host_ctr), sizeof(Counters),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         delete c;
         return FASTSV_ENOMEM;
+    }
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&c->dev_ctr), c->host_ctr, 0) != hipSuccess || !c->dev_ctr) {
+        fastsv_destroy(c);
+        return FASTSV_EHIP;
     }
     memset(c->host_ctr, 0, sizeof(Counters));
     // timing events are made here, so that no solve call creates runtime objects

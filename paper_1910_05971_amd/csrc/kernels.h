@@ -714,6 +714,14 @@ __global__ __launch_bounds__(kGpThreads) void k_frontier_from_mask(int n, const 
     }
 }
 
+// Copies iteration counters (to mapped host memory), one 64-bit word per lane.
+__global__ void k_publish_counters(const IterCounters *__restrict__ src, IterCounters *__restrict__ dst) {
+    constexpr int kWords = (int)(sizeof(IterCounters) / sizeof(unsigned long long));
+    const int i = threadIdx.x;
+    if (i < kWords)
+        reinterpret_cast<unsigned long long *>(dst)[i] = reinterpret_cast<const unsigned long long *>(src)[i];
+}
+
 __global__ void k_zero_iter_counters(IterCounters *c) {
     if (threadIdx.x == 0) {
         c->packed = 0ull;
