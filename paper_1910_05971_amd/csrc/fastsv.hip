@@ -343,6 +343,10 @@ struct fastsv_ctx {
     void *ws = nullptr;
     size_t ws_size = 0;
     hipEvent_t ev[6] = {};  // iteration phases; [4], [5] bracket the frontier list build
+    // the main loop's iteration phases, one set per traced iteration (read
+    // after the loop, so that timing adds no host work between iterations):
+    // start, hooking done, grandparent pass done, frontier list start and end
+    hipEvent_t tev[FASTSV_TRACE_ITERS][5] = {};
     bool events = false;
 };
 
@@ -638,6 +642,7 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
     bool frontier_ready = false;
     const double tau_edges = (double)opts.frontier_tau * (double)nnz;
     int64_t alg = 0;
+    bool listed[FASTSV_TRACE_ITERS] = {};  // traced iterations that built the frontier list
     for (;;) {
         ++it;
         int *F = w.F[(it + 1) & 1];
@@ -669,7 +674,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             bin_state = 1;
             if (stats) stats->num_bins = L.nbins;
         }
-        if (timed) HIP_TRY(hipEventRecord(ctx->ev[0], stream));
+        hipEvent_t *tv = timed ? ctx->tev[ti] : nullptr;
+        if (timed) HIP_TRY(hipEventRecord(tv[0], stream));
         if (sparse) {
             launch_sparse(stream, w.frontier, w.eoff, (int)prev_fcnt, (int)prev_edges, P.rp, P.col, P.vbase, F, Fn, G,
                           w.M, atom);
@@ -714,13 +720,13 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             // row_ptr, col, gathers of G[col] (none while G is the identity), then G[u], F[u], M[u] per row
             alg += 4 * ((int64_t)n + 1) + (gathers ? 8 : 4) * nnz + 12 * (int64_t)n + (base ? 4 * (int64_t)n : 0);
         }
-        if (timed) HIP_TRY(hipEventRecord(ctx->ev[1], stream));
+        if (timed) HIP_TRY(hipEventRecord(tv[1], stream));
         int64_t alg_hook = alg - alg_before;  // the hooking pass's bytes (completed below)
         const bool want_frontier = opts.frontier_tau > 0.0f;
         launch_grandparent(stream, n, Fn, G, F, P.rp, w.frontier, w.eoff, ic, want_frontier ? 2 : 0, P.lastk, it,
                            P.vbase, nullptr, w.fmask);
         HIP_TRY(hipGetLastError());
-        if (timed) HIP_TRY(hipEventRecord(ctx->ev[2], stream));
+        if (timed) HIP_TRY(hipEventRecord(tv[2], stream));
         launch_publish(stream, ic, &ctx->dev_ctr->it[it & 1]);
         HIP_TRY(hipStreamSynchronize(stream));
         const int64_t changed = (int64_t)(hc->packed >> 32);
@@ -741,10 +747,10 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         if (want_frontier && changed > 0 &&
             (opts.frontier_tau >= 1.0f ||
              ((double)changed <= tau_edges && (double)changed * (double)nnz <= 2.0 * tau_edges * (double)n))) {
-            if (timed) HIP_TRY(hipEventRecord(ctx->ev[4], stream));
+            if (timed) HIP_TRY(hipEventRecord(tv[3], stream));
             launch_frontier_from_mask(stream, n, w.fmask, P.rp, w.frontier, w.eoff, &w.ctr->fb);
             HIP_TRY(hipGetLastError());
-            if (timed) HIP_TRY(hipEventRecord(ctx->ev[5], stream));
+            if (timed) HIP_TRY(hipEventRecord(tv[4], stream));
             launch_publish(stream, &w.ctr->fb, &ctx->dev_ctr->fb);
             HIP_TRY(hipStreamSynchronize(stream));
             edges = (int64_t)(ctx->host_ctr->fb.packed & 0xffffffffull);
@@ -758,27 +764,8 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
             stats->pushed[ti] = sparse ? prev_edges : 0;
             stats->atomics[ti] = atomics;
             stats->alg_hook[ti] = alg_hook;
-            if (timed) {
-                float a = 0, b = 0;
-                HIP_TRY(hipEventElapsedTime(&a, ctx->ev[0], ctx->ev[1]));
-                HIP_TRY(hipEventElapsedTime(&b, ctx->ev[1], ctx->ev[2]));
-                if (it == 1 && fuse_first) {
-                    // the count and scan before the fill, and the fill itself
-                    float c = 0;
-                    HIP_TRY(hipEventElapsedTime(&c, ctx->ev[0], ctx->ev[3]));
-                    stats->ms_bin_prepare = c;
-                    a -= c;
-                }
-                if (list_ready) {
-                    // the frontier list build counts with the grandparent pass
-                    float l = 0;
-                    HIP_TRY(hipEventElapsedTime(&l, ctx->ev[4], ctx->ev[5]));
-                    b += l;
-                }
-                stats->ms_hook[ti] = a;
-                stats->ms_gp[ti] = b;
-            }
         }
+        if (timed) listed[ti] = list_ready;
         if (stats) {
             if (sparse) {
                 stats->sparse_iterations++;
@@ -795,6 +782,30 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
         if (opts.max_iters > 0 && it >= opts.max_iters) {
             status = FASTSV_ENOTCONVERGED;
             break;
+        }
+    }
+    if (stats && opts.timing) {
+        // the phases of every traced iteration, from its events
+        for (int ti = 0; ti < std::min(it, FASTSV_TRACE_ITERS); ++ti) {
+            hipEvent_t *tv = ctx->tev[ti];
+            float a = 0, b = 0;
+            HIP_TRY(hipEventElapsedTime(&a, tv[0], tv[1]));
+            HIP_TRY(hipEventElapsedTime(&b, tv[1], tv[2]));
+            if (ti == 0 && fuse_first) {
+                // the count and scan before the fill, and the fill itself
+                float c = 0;
+                HIP_TRY(hipEventElapsedTime(&c, tv[0], ctx->ev[3]));
+                stats->ms_bin_prepare = c;
+                a -= c;
+            }
+            if (listed[ti]) {
+                // the frontier list build counts with the grandparent pass
+                float l = 0;
+                HIP_TRY(hipEventElapsedTime(&l, tv[3], tv[4]));
+                b += l;
+            }
+            stats->ms_hook[ti] = a;
+            stats->ms_gp[ti] = b;
         }
     }
     if (stats) {
@@ -904,6 +915,12 @@ int fastsv_create(fastsv_ctx **out, int device) {
         }
         c->events = true;
     }
+    for (auto &set : c->tev)
+        for (auto &e : set)
+            if (hipEventCreate(&e) != hipSuccess) {
+                fastsv_destroy(c);
+                return FASTSV_EHIP;
+            }
     const int rs = resolve_scratch(device);
     if (rs != FASTSV_OK) {
         fastsv_destroy(c);
@@ -918,6 +935,9 @@ void fastsv_destroy(fastsv_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->events)
         for (auto &e : c->ev)
+            if (e) (void)hipEventDestroy(e);
+    for (auto &set : c->tev)
+        for (auto &e : set)
             if (e) (void)hipEventDestroy(e);
     if (c->ws) (void)hipFree(c->ws);
     if (c->host_ctr) (void)hipHostFree(c->host_ctr);

@@ -224,3 +224,23 @@ def test_trace_counts_atomics_without_changing_iterates(gpu_ok):
     torch.cuda.synchronize()
     assert torch.equal(lab1, lab2) and torch.equal(it1, it2)
     assert sb2.atomics_issued == sum(sb2.atomics_list()) > 0 and sb1.atomics_issued == -1
+
+
+def test_timing_stats(gpu_ok):
+    # opts.timing: every iteration's hooking and grandparent phases are timed
+    # (read after the loop), the fused layout build is split off, and the
+    # result and per-iteration counts are those of the untimed call
+    import paper_1910_05971_amd as fs
+    g = gg.er(300_000, 1_200_000, seed=77)
+    rp, col = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
+    for kw in ({"binned": True, "bin_shift": 12}, {"binned": False}, {"binned": True, "bin_shift": 12,
+                                                                       "frontier_tau": 0.5}):
+        plain, sp = fs.cc_csr(rp, col, **kw)
+        timed, st = fs.cc_csr(rp, col, timing=True, **kw)
+        assert torch.equal(plain, timed) and st.iterations == sp.iterations
+        assert st.changed_list() == sp.changed_list() and st.sparse_list() == sp.sparse_list()
+        k = min(st.iterations, 64)
+        assert all(st.ms_hook[i] > 0 for i in range(k)) and all(st.ms_gp[i] > 0 for i in range(k)), kw
+        assert all(sp.ms_hook[i] == 0 for i in range(k))
+        if kw["binned"]:
+            assert st.bin_fused_first == 1 and st.ms_bin_prepare > 0
