@@ -8,8 +8,8 @@ resident in HBM; value = undirected edges per second.
 
 Also in the same JSON line:
   roofline      the kernel with the most time per solve, of the binned dense
-                SpMV step (k_bin_pull<32> for R-MAT scale 24, whose bins are long
-                enough for the wide step, else <16>; one launch per iteration) and the layout
+                SpMV step (k_bin_pull<16> for R-MAT scale 24, whose bins are long,
+                <8> for short bins; one launch per iteration) and the layout
                 fill that also performs the first iteration (k_bin_fill<true>,
                 once per solve); the other one is in roofline_other.  Each:
                 algorithmic bytes per launch / its average launch time from HIP

@@ -114,8 +114,8 @@ typedef struct {
                                (FASTSV_ENOTCONVERGED), and the statistics below record the
                                per-iteration figures. */
     int32_t bin_span;       /* records per lane and step of the binned dense pass: 8, 16 or 32;
-                               0 = automatic (32 for bins of at least 2^18 records, 16 for at
-                               least 2^17, else 8).  Same iterates either way. */
+                               0 = automatic (16 for bins of at least 2^17 records, else 8).
+                               Same iterates either way. */
     int32_t admit_mb;       /* serving only: megabytes of graph data a server step admits once one
                                graph is in (1..4096; 0 = 128) */
 } fastsv_opts;

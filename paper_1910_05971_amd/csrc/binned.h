@@ -420,9 +420,27 @@ __global__ __launch_bounds__(1024) void k_bin_pull(int n, int W, int nchunks, in
             }
 #pragma unroll
             for (int x = 0; x < kPerLaneSpan; ++x) v[x] = G[v[x]];
+            if (kPerLaneSpan >= kBinSpan) {
+                // a record whose value is not below its row's current minimum
+                // changes nothing (the minima only decrease, so an older value
+                // read here only lets an atomic through), and in bins that
+                // give every row many records most are of this kind after the
+                // row's first few: the rows' minima are read first (all reads
+                // issued together, unconditionally) and only the records below
+                // them take an atomic.  (An LDS atomic costs per active lane;
+                // a row of k records in random order sees about ln k + 0.58
+                // new minima.)
+                int cur[kPerLaneSpan];
 #pragma unroll
-            for (int x = 0; x < kPerLaneSpan; ++x)
-                if (d[x] >= 0) atomicMin(&wmin[d[x]], v[x]);
+                for (int x = 0; x < kPerLaneSpan; ++x) cur[x] = wmin[max(d[x], 0)];
+#pragma unroll
+                for (int x = 0; x < kPerLaneSpan; ++x)
+                    if (d[x] >= 0 && v[x] < cur[x]) atomicMin(&wmin[d[x]], v[x]);
+            } else {
+#pragma unroll
+                for (int x = 0; x < kPerLaneSpan; ++x)
+                    if (d[x] >= 0) atomicMin(&wmin[d[x]], v[x]);
+            }
         }
         __syncthreads();
     }

@@ -88,14 +88,15 @@ constexpr int kBinShiftMin = 8;
 constexpr int kBinRowsMax = 40960;      // widest bin: a 160 KB LDS window in the dense pass
 constexpr int kNumCUs = 256;            // MI355X compute units: one dense-pass workgroup each at a time
 // entries per lane and step of the binned dense pass, by the bin's length in
-// records: a longer step leaves a longer ragged last step per bin, and a
-// shorter one keeps the workgroups of an XCD gathering from a narrower slice
-// of G at a time (bins whose sources spread over all of G: short bins)
+// records: a shorter step keeps the workgroups of an XCD gathering from a
+// narrower slice of G at a time (bins whose sources spread over all of G:
+// short bins); the spans from kBinSpan on read a row's minimum before its
+// atomic, which pays where rows get many records (long bins).  The wide span
+// is taken only when asked for.
 constexpr int kBinSpanNarrow = 8;       // bins of fewer than kBinMidMin records
-constexpr int kBinSpan = 16;            // bins of kBinMidMin to kBinWideMin records
-constexpr int kBinSpanWide = 32;        // bins of at least kBinWideMin records
+constexpr int kBinSpan = 16;            // bins of at least kBinMidMin records
+constexpr int kBinSpanWide = 32;
 constexpr int64_t kBinMidMin = 1 << 17;
-constexpr int64_t kBinWideMin = 1 << 18;
 constexpr int kFinishBatch = 8;         // rows per thread whose loads the dense pass's row finish batches
 constexpr int kBinThreads = 256;        // layout count pass
 constexpr int kFillThreads = 512;       // layout fill: one tile per wave and round

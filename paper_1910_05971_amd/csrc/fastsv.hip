@@ -693,13 +693,10 @@ int solve(fastsv_ctx *ctx, const Problem &P, const Layout &L, const Workspace &w
                 launch_dense(stream, base ? kDenseBaseIota : kDenseIota, w.tiles, (int)ntiles, P.rp, P.col, P.vbase,
                              F, Fn, G, w.M, atom);
             } else if (bin_state == 1) {
-                // wide steps only where bins are long enough that the ragged
-                // last step of each bin is a small share, narrow ones where
-                // they are short
+                // narrow steps where bins are short (their rows get few
+                // records), the filtered middle span otherwise
                 const int64_t per_bin = L.bin_cap / L.nbins;
-                const int span = opts.bin_span ? opts.bin_span
-                                               : per_bin >= kBinWideMin ? kBinSpanWide
-                                                                        : per_bin >= kBinMidMin ? kBinSpan : kBinSpanNarrow;
+                const int span = opts.bin_span ? opts.bin_span : per_bin >= kBinMidMin ? kBinSpan : kBinSpanNarrow;
                 if (span == kBinSpanWide)
                     hipLaunchKernelGGL(k_bin_pull<kBinSpanWide>, dim3(L.nbins), dim3(1024), 0, stream, n, L.bdiv.rows,
                                        L.nchunks, L.bin_cap, w.bcnt, w.brec, w.bck, F, Fn, G, w.M, atom);

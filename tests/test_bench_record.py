@@ -27,18 +27,18 @@ def test_roofline_record_arithmetic_and_lookup():
 
 def test_counter_record_names_the_benchmarked_kernels():
     # the R-MAT scale-24 record holds the kernels bench.py names for that
-    # workload (the dense step runs the wide-step instantiation there), each
+    # workload (the dense step runs the 16-record instantiation there), each
     # with a hash of the kernel sources it was taken with
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["rmat_scale24_ef16"]
-    for k in ("k_bin_pull<32>", "k_bin_fill<true>", "_solve"):
+    for k in ("k_bin_pull<16>", "k_bin_fill<true>", "_solve"):
         assert k in rec and len(rec[k]["kernel_source_sha256_16"]) == 16
-    assert rec["k_bin_pull<32>"]["hbm_bytes_per_launch"] > 0 and rec["_solve"]["hbm_bytes_per_solve"] > 0
+    assert rec["k_bin_pull<16>"]["hbm_bytes_per_launch"] > 0 and rec["_solve"]["hbm_bytes_per_solve"] > 0
     hashes = {rec[k]["kernel_source_sha256_16"] for k in rec}
     assert len(hashes) == 1  # one profiling run
     # while the sources are those the counters were taken with, bench.py reports them
     if hashes == {bench.kernel_source_hash()}:
-        r = bench.roofline_record("k_bin_pull<32>", "u", 1.0, 1.0, 1, 1, bench.kernel_source_hash(), rec)
-        assert r["traffic"] == rec["k_bin_pull<32>"]["hbm_bytes_per_launch"]
+        r = bench.roofline_record("k_bin_pull<16>", "u", 1.0, 1.0, 1, 1, bench.kernel_source_hash(), rec)
+        assert r["traffic"] == rec["k_bin_pull<16>"]["hbm_bytes_per_launch"]
 
 
 def test_more_than_one_gpu_is_refused():

@@ -195,11 +195,11 @@ def test_binned_passes_trajectories(gpu_ok):
 
 
 def test_binned_span_choice(gpu_ok):
-    # bins of at least 2^18 records take the wide dense step (32 records per
-    # lane and step), bins under 2^17 the narrow one (8), and 16 is chosen
-    # explicitly here; each is checked iterate by iterate
+    # bins of at least 2^17 records take the filtered middle step (16 records
+    # per lane and step), shorter ones the narrow one (8); 32 and 16 are also
+    # asked for explicitly; each is checked iterate by iterate
     g = gg.rmat(16, 16, seed=69)
-    for shift, ask, span in ((14, 0, 32), (10, 0, 8), (10, 16, 16)):
+    for shift, ask, span in ((14, 0, 16), (14, 32, 32), (10, 0, 8), (10, 16, 16)):
         check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift, bin_span=ask)
         rp, col = to_dev(g)
         _, st = solve(rp, col, frontier_tau=0.0, binned=True, bin_shift=shift, bin_span=ask)
