@@ -141,6 +141,11 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
     __shared__ __align__(16) int sv[kWaves * kTileEntries];  // staged sources
     __shared__ __align__(16) int su[kWaves * kTileEntries];  // staged columns
     __shared__ int s_wsum[kWaves];
+    // the descriptors of the next kTileWin tiles; a round reads its tiles'
+    // bounds here instead of from global memory
+    constexpr int kTileWin = kBinChunkTilesMin;
+    static_assert(kTileWin % kWaves == 0, "a descriptor window holds whole rounds");
+    __shared__ Tile s_tw[kTileWin];
     // the wave's window of row starts and (first iteration) its per-row minima
     // live from the round's start to its second barrier, the staged entries
     // after it, so they share memory (the windows and minima of all waves take
@@ -174,18 +179,27 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
         }
         hi_done = h;
     };
+    int tw_base = 0, tw_end = 0;
     for (int t0 = k * chunk_tiles; t0 < t_end; t0 += kWaves) {
+      if (t0 >= tw_end) {
+          // every wave has passed its last read of the previous window: the
+          // previous pass ended with a barrier after them
+          tw_base = t0;
+          tw_end = min(t0 + kTileWin, t_end);
+          if (tid < tw_end - tw_base) s_tw[tid] = tiles[tw_base + tid];
+          __syncthreads();
+      }
       // high source bits of the round's rows: one value unless they cross a
       // boundary; then the round is processed once per value, each pass
       // placing the entries of its value only
-      const int h_first = hi_of(tiles[t0].r_lo);
-      const int h_last = max(hi_of(tiles[min(t0 + kWaves, t_end) - 1].r_hi), h_first);
+      const int h_first = hi_of(s_tw[t0 - tw_base].r_lo);
+      const int h_last = max(hi_of(s_tw[min(t0 + kWaves, t_end) - 1 - tw_base].r_hi), h_first);
       for (int h = h_first; h <= h_last; ++h) {
         const bool one = h_first == h_last;
         const bool first_pass = h == h_first;
         const int t = t0 + wave;
         const bool tile_ok = t < t_end;
-        const Tile T = tile_ok ? tiles[t] : Tile{0, 0, 0, -1};
+        const Tile T = tile_ok ? s_tw[t - tw_base] : Tile{0, 0, 0, -1};
         const int a = T.e0 + lane * kPerLane;
         const int cnt = tile_ok ? max(0, min(kPerLane, T.e1 - a)) : 0;
         int c[kPerLane];
@@ -242,27 +256,71 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
             }
         }
         const int *wrow = winw;
-        auto rpw = [&](int r) -> int { return in_lds ? wrow[r - T.r_lo] : rp[r]; };
         // source row of every entry and its rank inside its bin in this round
-        int row = T.r_lo, nxt = 0;
-        if (cnt > 0) {
-            int lo = T.r_lo, hi = T.r_hi;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rpw(mid) <= a) lo = mid;
-                else hi = mid - 1;
-            }
-            row = lo;
-            nxt = rpw(row + 1);
-        }
         int r[kPerLane], rank[kPerLane];
+        if (in_lds) {
+            // every non-empty row of the window writes its index at its first
+            // entry in the tile, and a running maximum over the tile's entries
+            // carries it on to the rest of the row; the words are the wave's
+            // staging halves, free from the regroup's reads to the staging
+            constexpr int kHalf = kTileEntries / 2;
+            int *lo_half = su + kWaves * kRowWin + wave * kHalf;
+            int *hi_half = sv + kWaves * kRowWin + wave * kHalf;
+            const int x0 = kPerLane * lane;
+            v4i *mine = reinterpret_cast<v4i *>(x0 < kHalf ? lo_half + x0 : hi_half + (x0 - kHalf));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-        for (int j = 0; j < kPerLane; ++j) {
-            if (j < cnt) {
-                const int e = a + j;
-                while (e >= nxt) { ++row; nxt = rpw(row + 1); }
+            for (int q = 0; q < kPerLane / 4; ++q) mine[q] = v4i{0, 0, 0, 0};
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int nrows = nwin - 1;
+            for (int i = lane; i < nrows; i += kWave) {
+                const int s0 = wrow[i] - T.e0, s1 = wrow[i + 1] - T.e0;
+                if (s1 > s0 && s1 > 0 && s0 < kTileEntries) {
+                    const int x = max(s0, 0);
+                    *(x < kHalf ? lo_half + x : hi_half + (x - kHalf)) = i;
+                }
             }
-            r[j] = row;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            int m = 0;
+#pragma unroll
+            for (int q = 0; q < kPerLane / 4; ++q) {
+                const v4i w = mine[q];
+                m = max(m, w.x); r[4 * q] = m;
+                m = max(m, w.y); r[4 * q + 1] = m;
+                m = max(m, w.z); r[4 * q + 2] = m;
+                m = max(m, w.w); r[4 * q + 3] = m;
+            }
+            const int carry = wave_shift_up1(wave_incl_max_nonneg(m));
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) r[j] = T.r_lo + max(r[j], carry);
+        } else {
+            // rows too far apart for the window: a binary search in row_ptr
+            // for the lane's first entry, then a walk
+            int row = T.r_lo, nxt = 0;
+            if (cnt > 0) {
+                int lo = T.r_lo, hi = T.r_hi;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (rp[mid] <= a) lo = mid;
+                    else hi = mid - 1;
+                }
+                row = lo;
+                nxt = rp[row + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < kPerLane; ++j) {
+                if (j < cnt) {
+                    const int e = a + j;
+                    while (e >= nxt) { ++row; nxt = rp[row + 1]; }
+                }
+                r[j] = row;
+            }
         }
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
@@ -319,22 +377,32 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
             o += hist[b];
         }
         __syncthreads();
+        // the stage holds, in bin order, every entry's record and its position
+        // in the layout, so that the write-out reads two words per entry
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
             if (rank[j] >= 0) {
-                const int sidx = loff[bin_of(c[j], bd)] + rank[j];
-                sv[sidx] = r[j];
-                su[sidx] = c[j];
+                const int b = bin_of(c[j], bd);
+                const int sidx = loff[b] + rank[j];
+                sv[sidx] = (int)(((unsigned)r[j] << kSrcLoBits) | (unsigned)(c[j] - b * bd.rows));
+                su[sidx] = cur[b] + rank[j];
             }
         }
         __syncthreads();
-        for (int sidx = tid; sidx < total; sidx += kFillThreads) {
-            const int u = su[sidx];
-            const int b = bin_of(u, bd);
-            const int pos = cur[b] + (sidx - loff[b]);
-            if (pos < cap) {
-                brec[pos] = ((unsigned)sv[sidx] << kSrcLoBits) | (unsigned)(u - b * bd.rows);
-                if ((pos & kCkMask) == 0) bck[pos >> kBinCkShift] = h;
+        constexpr int kOut = kWaves * kTileEntries / kFillThreads;
+        unsigned rec[kOut];
+        int pos[kOut];
+#pragma unroll
+        for (int q = 0; q < kOut; ++q) {
+            const int sidx = tid + q * kFillThreads;
+            pos[q] = sidx < total ? su[sidx] : cap;
+            rec[q] = (unsigned)sv[sidx];
+        }
+#pragma unroll
+        for (int q = 0; q < kOut; ++q) {
+            if (pos[q] < cap) {
+                brec[pos[q]] = rec[q];
+                if ((pos[q] & kCkMask) == 0) bck[pos[q] >> kBinCkShift] = h;
             }
         }
         __syncthreads();

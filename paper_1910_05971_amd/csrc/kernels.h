@@ -35,6 +35,25 @@ __device__ __forceinline__ int wave_incl_sum(int v) {
     return v;
 }
 
+// Inclusive max-scan over the lanes of a wave for values >= 0, with DPP lane
+// moves (0 stands in for the lanes a move has no source for): shifts by 1, 2,
+// 4 and 8 within each row of 16 lanes, then lane 15 into row 1 and lane 47
+// into row 3, then lane 31 into rows 2 and 3.
+__device__ __forceinline__ int wave_incl_max_nonneg(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+// The value of the previous lane (0 in lane 0).
+__device__ __forceinline__ int wave_shift_up1(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+
 // Aggressive hook Fn[u] <-min m and stochastic hook Fn[F[u]] <-min m of a
 // row whose minimum m is below G[u].  Fn only decreases while hooks run, so a
 // read that already shows a value <= m (possibly an older one) proves the
