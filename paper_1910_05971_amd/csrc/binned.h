@@ -138,8 +138,12 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
     int *cur = s_dyn;               // next free position of the bin's run
     int *hist = s_dyn + nbins;      // round's count per bin
     int *loff = s_dyn + 2 * nbins;  // round's exclusive offset per bin in the stage
-    __shared__ __align__(16) int sv[kWaves * kTileEntries];  // staged sources
-    __shared__ __align__(16) int su[kWaves * kTileEntries];  // staged columns
+    // the round's stage: every entry's record and layout position, in bin
+    // order; before the stage is written its two halves (su, sv) hold the
+    // waves' row windows, row minima and regrouped tiles
+    __shared__ __align__(16) int2 s_stage[kWaves * kTileEntries];
+    int *su = reinterpret_cast<int *>(s_stage);
+    int *sv = su + kWaves * kTileEntries;
     __shared__ int s_wsum[kWaves];
     // the descriptors of the next kTileWin tiles; a round reads its tiles'
     // bounds here instead of from global memory
@@ -377,15 +381,12 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
             o += hist[b];
         }
         __syncthreads();
-        // the stage holds, in bin order, every entry's record and its position
-        // in the layout, so that the write-out reads two words per entry
 #pragma unroll
         for (int j = 0; j < kPerLane; ++j) {
             if (rank[j] >= 0) {
                 const int b = bin_of(c[j], bd);
-                const int sidx = loff[b] + rank[j];
-                sv[sidx] = (int)(((unsigned)r[j] << kSrcLoBits) | (unsigned)(c[j] - b * bd.rows));
-                su[sidx] = cur[b] + rank[j];
+                s_stage[loff[b] + rank[j]] =
+                    int2{(int)(((unsigned)r[j] << kSrcLoBits) | (unsigned)(c[j] - b * bd.rows)), cur[b] + rank[j]};
             }
         }
         __syncthreads();
@@ -395,8 +396,9 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
 #pragma unroll
         for (int q = 0; q < kOut; ++q) {
             const int sidx = tid + q * kFillThreads;
-            pos[q] = sidx < total ? su[sidx] : cap;
-            rec[q] = (unsigned)sv[sidx];
+            const int2 e = s_stage[sidx];
+            pos[q] = sidx < total ? e.y : cap;
+            rec[q] = (unsigned)e.x;
         }
 #pragma unroll
         for (int q = 0; q < kOut; ++q) {

@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kGpThreads) void k_grandparent(
         deg[i] = 0;
         if (u < n) {
             int p = Fn[u];
-            int g = Fn[p];
+            int g = p == u ? p : Fn[p];  // (a root is its own grandparent)
             int old = G[u];
             next_fn[u] = g;
             if (g != old) {
