@@ -178,6 +178,30 @@ def test_sparse_rows_wide_windows(gpu_ok):
     assert st.num_bins == 256 and st.bin_fused_first == 1
 
 
+def test_binned_fill_window_edge(gpu_ok):
+    # a cycle with sparse chords: its tiles of 1024 entries span 511 rows (the
+    # fill's row window full, rows found by the scan over row starts) or 512-513
+    # (one more than the window holds: rows found by searching row_ptr), mixed
+    # in one layout build; checked iterate by iterate from the fused first
+    # iteration on
+    rng = np.random.default_rng(73)
+    n = 200_000
+    pairs = [(i, (i + 1) % n) for i in range(n)]
+    pairs += [(int(a), int((a + n // 2 + 7) % n)) for a in rng.choice(n, 150, replace=False)]
+    rp_h, col_h = P.csr_from_pairs(n, pairs)
+    g = gg.Graph("chorded_cycle", n, rp_h, col_h, len(pairs))
+    nnz = int(rp_h[-1])
+    spans = []
+    for e0 in range(0, nnz, 1024):
+        e1 = min(nnz, e0 + 1024)
+        r_lo = int(np.searchsorted(rp_h, e0, side="right")) - 1
+        r_hi = int(np.searchsorted(rp_h, e1 - 1, side="right")) - 1
+        spans.append(r_hi - r_lo + 1)
+    assert 511 in spans and max(spans) > 511
+    for shift in (12, 15):
+        check_graph(g, taus=(0.0, 0.05), trajectory=True, binned=True, bin_shift=shift)
+
+
 def test_binned_passes_trajectories(gpu_ok):
     # binned dense passes forced on moderate graphs with narrow bins: many bins,
     # bins shorter than one block-wide span of the dense pass (32768 entries),
