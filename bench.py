@@ -426,11 +426,18 @@ def bench_batch(fs, torch, np, tuned=True):
     t_plain = time.perf_counter() - t
     del subs, vo, eo, rp, col, labels, iters
     torch.cuda.empty_cache()
+    # the whole batch against HBM: the library's algorithmic bytes over the
+    # union graph's executed iterations (dense or sparse passes and
+    # grandparent passes, as for one solve) per batch time
+    alg = int(st.alg_bytes)
+    batch_roofline = {"alg_bytes": alg, "ms": 1000 * t_batch, "achieved": alg / t_batch / 1e9, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": alg / t_batch / 1e9 / HBM_PEAK_GBS,
+                      "dense_iterations": int(st.dense_iterations), "sparse_iterations": int(st.sparse_iterations)}
     out = {"workload": "4096 Erdos-Renyi graphs, n log-uniform in [64, 65536), average degree uniform in [2, 32]",
            "graphs": b.num_graphs, "total_edges_undirected": int(b.m_eff.sum()),
            "graphs_per_s": b.num_graphs / t_batch, "ms_per_batch": 1000 * t_batch,
            "iterations": st.iterations, "plain_graphs_per_s": b.num_graphs / t_plain,
-           "speedup_vs_plain": t_plain / t_batch, "tuning": tuning}
+           "speedup_vs_plain": t_plain / t_batch, "tuning": tuning, "solve_roofline": batch_roofline}
     return out, (b, gpu_labels, gpu_iters)
 
 
