@@ -380,7 +380,7 @@ def host_info():
 
 def oracle_workers():
     """Threads for the oracle's all-core runs: the cores this process may use,
-    at most 16 (the GPU machine's CPU share).  ctypes releases the GIL during each
+    at most 16 (a one-GPU host's share of cores).  ctypes releases the GIL during each
     oracle call, so threads run the C oracle in parallel."""
     return max(1, min(16, host_info()["usable_cores"]))
 
@@ -619,7 +619,7 @@ def cpu_oracle_table(np, c2, c2_iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
