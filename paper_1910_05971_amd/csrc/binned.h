@@ -124,13 +124,12 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t nnz, int n, c
 // since f is the identity too); it replaces the first pull pass.
 // Dynamic LDS: 3 * nbins ints.
 template <bool kFirst>
-__global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n,
-                                                          const int *__restrict__ rp, const int *__restrict__ col,
-                                                          BinDiv bd, int nbins, int nchunks, int chunk_tiles,
-                                                          const int *__restrict__ off, int cap,
-                                                          unsigned *__restrict__ brec, int *__restrict__ bck,
-                                                          int *__restrict__ M, int *__restrict__ Fn,
-                                                          unsigned long long *__restrict__ atom) {
+// (at most 128 VGPRs: two workgroups of 8 waves share a CU)
+__global__ __launch_bounds__(kFillThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_bin_fill(const Tile *__restrict__ tiles, int ntiles, int n, const int *__restrict__ rp, const int *__restrict__ col,
+           BinDiv bd, int nbins, int nchunks, int chunk_tiles, const int *__restrict__ off, int cap,
+           unsigned *__restrict__ brec, int *__restrict__ bck, int *__restrict__ M, int *__restrict__ Fn,
+           unsigned long long *__restrict__ atom) {
     constexpr int kWaves = kFillThreads / kWave;
     constexpr int kCkMask = (1 << kBinCkShift) - 1;
     static_assert(2 * kRowWin <= kTileEntries, "row windows, row minima and the regrouped loads share the staging arrays");
@@ -226,11 +225,32 @@ __global__ __launch_bounds__(kFillThreads) void k_bin_fill(const Tile *__restric
         }
         const int nwin = T.r_hi - T.r_lo + 2;
         const bool in_lds = tile_ok && nwin <= kRowWin;
-        if (in_lds)
-            for (int j = lane; j < nwin; j += kWave) {
-                winw[j] = rp[T.r_lo + j];
-                if (kFirst) rminw[j] = INT_MAX;
+        if (in_lds) {
+            // a window of at most 64 row starts takes one load per lane; a wider
+            // one has all of its loads issued before the first is stored
+            if (nwin <= kWave) {
+                if (lane < nwin) {
+                    winw[lane] = rp[T.r_lo + lane];
+                    if (kFirst) rminw[lane] = INT_MAX;
+                }
+            } else {
+                constexpr int kWinLoads = kRowWin / kWave;
+                int wv[kWinLoads];
+#pragma unroll
+                for (int q = 0; q < kWinLoads; ++q) {
+                    const int j = lane + q * kWave;
+                    wv[q] = j < nwin ? rp[T.r_lo + j] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < kWinLoads; ++q) {
+                    const int j = lane + q * kWave;
+                    if (j < nwin) {
+                        winw[j] = wv[q];
+                        if (kFirst) rminw[j] = INT_MAX;
+                    }
+                }
             }
+        }
         __syncthreads();
         if (whole) {
             // tile entries [0, 512) pass through su, [512, 1024) through sv,
